@@ -1,0 +1,516 @@
+// Device kernels of the tweed / wireframe multigrid (gfx950).
+//
+// Everything here is memory-bound stencil or line-solve work (about half a
+// flop per byte), so no MFMA: the design goals are single-pass HBM traffic,
+// coalesced rows and enough independent waves per CU.
+#include "sweep_core.h"
+
+namespace twmg {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// defect f - L u at interior node (i, j, l) with linear index p
+template <typename T, int DIM>
+__device__ __forceinline__ T defect_at(const Dims &d, const Coef<T> &cf, const T *__restrict__ u,
+                                       const T *__restrict__ f, int i, int j, int l, long long p)
+{
+    T s = cf.lo[0][i] * u[p - 1] + cf.hi[0][i] * u[p + 1];
+    s += cf.lo[1][j] * u[p - d.st[1]] + cf.hi[1][j] * u[p + d.st[1]];
+    T dg = cf.dg[0][i] + cf.dg[1][j];
+    if (DIM == 3) {
+        s += cf.lo[2][l] * u[p - d.st[2]] + cf.hi[2][l] * u[p + d.st[2]];
+        dg += cf.dg[2][l];
+    }
+    return f[p] - (s + dg * u[p]);
+}
+
+template <int DIM> __device__ __forceinline__ bool interior(const Dims &d, int i, int j, int l)
+{
+    bool in = i > 0 && i < d.n[0] && j > 0 && j < d.n[1];
+    if (DIM == 3) in = in && l > 0 && l < d.n[2];
+    return in;
+}
+
+// rows of a node array: (j, l) pairs; row r -> j = r % (ny+1), l = r / (ny+1)
+__device__ __forceinline__ int nrows(const Dims &d, int DIM)
+{
+    return (d.n[1] + 1) * (DIM == 3 ? d.n[2] + 1 : 1);
+}
+
+// ---------------------------------------------------------------------------
+// Block relaxation half-sweep: one workgroup per group of whole blocks of one
+// colour; the per-lane steps are in sweep_core.h.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+                                                    const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
+                                                    const WGDesc *__restrict__ wgs)
+{
+    __shared__ T s_low[NT], s_ds[NT], s_rs[NT], s_dn[NT], s_up[NT], s_rn[NT], s_x[NT], s_aux[NT];
+    const RedArrays<T> red{s_low, s_ds, s_rs, s_dn, s_up, s_rn, s_x, s_aux};
+    const WGDesc w = wgs[blockIdx.x];
+    const long long boff = (long long)blockIdx.y * d.nn;
+    T *__restrict__ ub = u + boff;
+    const T *__restrict__ fb = f + boff;
+    const int t = threadIdx.x;
+    const bool act = t < w.nchunk;
+    LaneState<T> st;
+    if (act) sweep_phase1<T, DIM>(d, cf, ub, fb, chunks[w.chunk0 + t], t, red, st);
+    __syncthreads();
+    if (t < w.nblock) reduced_solve<T>(blocks[w.block0 + t], red);
+    __syncthreads();
+    if (act) sweep_phase3<T>(ub, t, red, st);
+}
+
+template <typename T>
+hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int batch,
+                              hipStream_t s)
+{
+    if (tab.nwg == 0) return hipSuccess;
+    dim3 grid(tab.nwg, batch);
+    if (d.dim == 2)
+        hipLaunchKernelGGL((k_block_sweep<T, 2>), grid, dim3(NT), 0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs);
+    else
+        hipLaunchKernelGGL((k_block_sweep<T, 3>), grid, dim3(NT), 0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Checkerboard (red-black point Gauss-Seidel) half-sweep: Section 2, Fig. 1.
+// red = (i + j [+ l]) even.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_checker(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+                                                 int colour)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    T *ub = u + boff;
+    const T *fb = f + boff;
+    const int rows = nrows(d, DIM);
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int j = r % (d.n[1] + 1), l = r / (d.n[1] + 1);
+        if (j == 0 || j == d.n[1] || (DIM == 3 && (l == 0 || l == d.n[2]))) continue;
+        const int i0 = 1 + ((1 + j + l + colour) & 1);
+        for (int i = i0 + 2 * threadIdx.x; i < d.n[0]; i += 2 * blockDim.x) {
+            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            T s = fb[p] - cf.lo[0][i] * ub[p - 1] - cf.hi[0][i] * ub[p + 1] - cf.lo[1][j] * ub[p - d.st[1]] -
+                  cf.hi[1][j] * ub[p + d.st[1]];
+            if (DIM == 3) s -= cf.lo[2][l] * ub[p - d.st[2]] + cf.hi[2][l] * ub[p + d.st[2]];
+            ub[p] = s / diag_at<T, DIM>(cf, i, j, l);
+        }
+    }
+}
+
+static int row_grid(const Dims &d) { int r = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1); return r < 65535 ? r : 65535; }
+
+template <typename T>
+hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(d), batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_checker<T, 2>), grid, dim3(256), 0, s, d, c, u, f, colour);
+    else hipLaunchKernelGGL((k_checker<T, 3>), grid, dim3(256), 0, s, d, c, u, f, colour);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Defect d = f - L u (Section 4 step 3), 0 on boundary nodes.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_residual(Dims d, Coef<T> cf, const T *__restrict__ u,
+                                                  const T *__restrict__ f, T *__restrict__ r)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    const int rows = nrows(d, DIM);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
+        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
+            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            r[boff + p] = interior<DIM>(d, i, j, l) ? defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l, p) : T(0);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_residual(const Dims &d, const Coef<T> &c, const T *u, const T *f, T *r, int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(d), batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_residual<T, 2>), grid, dim3(256), 0, s, d, c, u, f, r);
+    else hipLaunchKernelGGL((k_residual<T, 3>), grid, dim3(256), 0, s, d, c, u, f, r);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused defect + full-weighting restriction (Section 4, fused step 3): one
+// thread per coarse interior node sums (1/4,1/2,1/4)^dim weighted fine defects
+// around fine node 2I; also clears the coarse correction u_c there (step 4).
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coef<T> cf, const T *__restrict__ u,
+                                                           const T *__restrict__ f, T *__restrict__ fc,
+                                                           T *__restrict__ uc)
+{
+    const T *ub = u + (long long)blockIdx.y * fd.nn;
+    const T *fb = f + (long long)blockIdx.y * fd.nn;
+    const long long cboff = (long long)blockIdx.y * cd.nn;
+    const int rows = nrows(cd, DIM);
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int J = row % (cd.n[1] + 1), K = row / (cd.n[1] + 1);
+        if (J == 0 || J == cd.n[1] || (DIM == 3 && (K == 0 || K == cd.n[2]))) continue;
+        for (int I = 1 + threadIdx.x; I < cd.n[0]; I += blockDim.x) {
+            T acc = 0;
+#pragma unroll
+            for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
+#pragma unroll
+                for (int b = -1; b <= 1; ++b) {
+                    T rowacc = 0;
+#pragma unroll
+                    for (int a = -1; a <= 1; ++a) {
+                        const int i = 2 * I + a, j = 2 * J + b, l = (DIM == 3) ? 2 * K + c : 0;
+                        if (interior<DIM>(fd, i, j, l)) {
+                            const long long p = i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0);
+                            rowacc += w3[a + 1] * defect_at<T, DIM>(fd, cf, ub, fb, i, j, l, p);
+                        }
+                    }
+                    acc += (DIM == 3 ? w3[c + 1] : T(1)) * w3[b + 1] * rowacc;
+                }
+            }
+            const long long q = cboff + I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0);
+            fc[q] = acc;
+            uc[q] = T(0);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
+                                    T *uc, int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(cd), batch);
+    if (fd.dim == 2) hipLaunchKernelGGL((k_residual_restrict<T, 2>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+    else hipLaunchKernelGGL((k_residual_restrict<T, 3>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused bilinear/trilinear prolongation + update (Section 4, fused step 5):
+// u += P e_c in index space; e_c's boundary entries are zero.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
+{
+    T *ub = u + (long long)blockIdx.y * fd.nn;
+    const T *eb = ec + (long long)blockIdx.y * cd.nn;
+    const int rows = nrows(fd, DIM);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (fd.n[1] + 1), l = row / (fd.n[1] + 1);
+        if (j == 0 || j == fd.n[1] || (DIM == 3 && (l == 0 || l == fd.n[2]))) continue;
+        const int J0 = j >> 1, J1 = (j + 1) >> 1;
+        const int K0 = l >> 1, K1 = (l + 1) >> 1;
+        for (int i = 1 + threadIdx.x; i < fd.n[0]; i += blockDim.x) {
+            const int I0 = i >> 1, I1 = (i + 1) >> 1;
+            // weights 1 (even index) or 1/2 + 1/2 (odd index) per axis
+            auto cval = [&](int I, int J, int K) -> T {
+                return eb[I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0)];
+            };
+            T v;
+            if (DIM == 2) {
+                const T r0 = (I0 == I1) ? cval(I0, J0, 0) : T(0.5) * (cval(I0, J0, 0) + cval(I1, J0, 0));
+                const T r1 = (I0 == I1) ? cval(I0, J1, 0) : T(0.5) * (cval(I0, J1, 0) + cval(I1, J1, 0));
+                v = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
+            } else {
+                T pl[2];
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const int K = kk ? K1 : K0;
+                    const T r0 = (I0 == I1) ? cval(I0, J0, K) : T(0.5) * (cval(I0, J0, K) + cval(I1, J0, K));
+                    const T r1 = (I0 == I1) ? cval(I0, J1, K) : T(0.5) * (cval(I0, J1, K) + cval(I1, J1, K));
+                    pl[kk] = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
+                }
+                v = (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
+            }
+            ub[i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0)] += v;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(fd), batch);
+    if (fd.dim == 2) hipLaunchKernelGGL((k_prolong_add<T, 2>), grid, dim3(256), 0, s, fd, cd, ec, u);
+    else hipLaunchKernelGGL((k_prolong_add<T, 3>), grid, dim3(256), 0, s, fd, cd, ec, u);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest-level direct solve (Section 4 step 4): u_I = A_II^{-1}(f_I - A_IB u_B)
+// with the inverse precomputed at setup; one workgroup per batch problem.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_coarse_solve(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+                                                      const T *__restrict__ ainv, int nunk)
+{
+    __shared__ T rhs[1024];
+    T *ub = u + (long long)blockIdx.x * d.nn;
+    const T *fb = f + (long long)blockIdx.x * d.nn;
+    const int nx = d.n[0] - 1, ny = d.n[1] - 1;
+    for (int q = threadIdx.x; q < nunk; q += blockDim.x) {
+        const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = (DIM == 3) ? 1 + q / (nx * ny) : 0;
+        const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+        T r = fb[p];
+        if (i == 1) r -= cf.lo[0][i] * ub[p - 1];
+        if (i == nx) r -= cf.hi[0][i] * ub[p + 1];
+        if (j == 1) r -= cf.lo[1][j] * ub[p - d.st[1]];
+        if (j == ny) r -= cf.hi[1][j] * ub[p + d.st[1]];
+        if (DIM == 3) {
+            const int nz = d.n[2] - 1;
+            if (l == 1) r -= cf.lo[2][l] * ub[p - d.st[2]];
+            if (l == nz) r -= cf.hi[2][l] * ub[p + d.st[2]];
+        }
+        rhs[q] = r;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nunk; q += blockDim.x) {
+        T s = 0;
+        for (int k = 0; k < nunk; ++k) s += ainv[(long long)q * nunk + k] * rhs[k];
+        const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = (DIM == 3) ? 1 + q / (nx * ny) : 0;
+        ub[i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0)] = s;
+    }
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f, const T *ainv, int nunk, int batch,
+                               hipStream_t s)
+{
+    if (d.dim == 2) hipLaunchKernelGGL((k_coarse_solve<T, 2>), dim3(batch), dim3(256), 0, s, d, c, u, f, ainv, nunk);
+    else hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(batch), dim3(256), 0, s, d, c, u, f, ainv, nunk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Infinity norm of the defect over interior nodes (Section 4 stopping rule):
+// per-workgroup maxima, then one workgroup reduces them.  Maxima are order
+// independent, so the result is bitwise reproducible.  Optionally writes the
+// defect rounded to FP32 (iterative refinement's right-hand side).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double s[16];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) s[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        v = (lane < (int)(blockDim.x >> 6)) ? s[lane] : 0.0;
+        v = wave_max(v);
+    }
+    return v;
+}
+
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || b != b) ? __builtin_nan("") : fmax(a, b); }
+
+template <typename T, int DIM, bool TO32>
+__global__ void __launch_bounds__(256) k_resnorm(Dims d, Coef<T> cf, const T *__restrict__ u, const T *__restrict__ f,
+                                                 float *__restrict__ r32, double *__restrict__ partial)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    const int rows = nrows(d, DIM);
+    double m = 0.0;
+    bool nan = false;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
+        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
+            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            T r = 0;
+            if (interior<DIM>(d, i, j, l)) r = defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l, p);
+            if (TO32) r32[boff + p] = (float)r;
+            const double a = fabs((double)r);
+            nan = nan || (a != a);
+            m = fmax(m, a);
+        }
+    }
+    if (nan) m = __builtin_inf();
+    m = block_max(m);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(256) k_max_final(const double *__restrict__ partial, int n, double *__restrict__ out)
+{
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, partial[k]);
+    m = block_max(m);
+    if (threadIdx.x == 0) out[0] = m;
+}
+
+template <typename T>
+hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *f, double *partial, int npart,
+                          double *out, int batch, hipStream_t s)
+{
+    int gx = npart / batch;
+    if (gx < 1) return hipErrorInvalidValue;
+    const int rows = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1);
+    if (gx > rows) gx = rows;
+    dim3 grid(gx, batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<T, 2, false>), grid, dim3(256), 0, s, d, c, u, f, nullptr, partial);
+    else hipLaunchKernelGGL((k_resnorm<T, 3, false>), grid, dim3(256), 0, s, d, c, u, f, nullptr, partial);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const double *u, const double *f, float *r32,
+                                 double *partial, int npart, double *out, int batch, hipStream_t s)
+{
+    int gx = npart / batch;
+    if (gx < 1) return hipErrorInvalidValue;
+    const int rows = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1);
+    if (gx > rows) gx = rows;
+    dim3 grid(gx, batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<double, 2, true>), grid, dim3(256), 0, s, d, c, u, f, r32, partial);
+    else hipLaunchKernelGGL((k_resnorm<double, 3, true>), grid, dim3(256), 0, s, d, c, u, f, r32, partial);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
+    return hipGetLastError();
+}
+
+// u += e at interior nodes (FP64 update of iterative refinement)
+template <int DIM> __global__ void __launch_bounds__(256) k_ir_update(Dims d, double *__restrict__ u, const float *__restrict__ e)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    const int rows = nrows(d, DIM);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
+        if (j == 0 || j == d.n[1] || (DIM == 3 && (l == 0 || l == d.n[2]))) continue;
+        for (int i = 1 + threadIdx.x; i < d.n[0]; i += blockDim.x) {
+            const long long p = boff + i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            u[p] += (double)e[p];
+        }
+    }
+}
+
+hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(d), batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_ir_update<2>), grid, dim3(256), 0, s, d, u, e);
+    else hipLaunchKernelGGL((k_ir_update<3>), grid, dim3(256), 0, s, d, u, e);
+    return hipGetLastError();
+}
+
+// boundary nodes <- bc (when given), interior <- 0 (when asked)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_set_boundary(Dims d, double *__restrict__ u, const double *__restrict__ bc,
+                                                      int zero_interior)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    const int rows = nrows(d, DIM);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
+        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
+            const long long p = boff + i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            if (interior<DIM>(d, i, j, l)) {
+                if (zero_interior) u[p] = 0.0;
+            } else if (bc) {
+                u[p] = bc[p];
+            }
+        }
+    }
+}
+
+hipError_t launch_set_boundary(const Dims &d, double *u, const double *bc, int zero_interior, int batch,
+                               hipStream_t s)
+{
+    dim3 grid(row_grid(d), batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_set_boundary<2>), grid, dim3(256), 0, s, d, u, bc, zero_interior);
+    else hipLaunchKernelGGL((k_set_boundary<3>), grid, dim3(256), 0, s, d, u, bc, zero_interior);
+    return hipGetLastError();
+}
+
+template <typename T> __global__ void __launch_bounds__(256) k_fill(T *__restrict__ p, long long n, T v)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+template <typename T> hipError_t launch_fill(T *p, long long n, T v, hipStream_t s)
+{
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Boundary-data gradient of L = sum(w u):  g_b = w_b - sum_{interior q ~ b} A[q,b] lam_q
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bc_grad(Dims d, Coef<double> cf, const double *__restrict__ lam,
+                                                 const double *__restrict__ w, double *__restrict__ g)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    const int rows = nrows(d, DIM);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
+        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
+            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+            if (interior<DIM>(d, i, j, l)) {
+                g[boff + p] = 0.0;
+                continue;
+            }
+            double s = w[boff + p];
+            const int c[3] = {i, j, l};
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    int q[3] = {c[0], c[1], c[2]};
+                    q[a] += sgn;
+                    if (q[a] < 0 || q[a] > d.n[a]) continue;
+                    if (!interior<DIM>(d, q[0], q[1], q[2])) continue;
+                    // row q's coefficient pointing back at p (direction -sgn along a)
+                    const double A = (sgn > 0) ? cf.lo[a][q[a]] : cf.hi[a][q[a]];
+                    s -= A * lam[boff + p + sgn * d.st[a]];
+                }
+            }
+            g[boff + p] = s;
+        }
+    }
+}
+
+hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *lam, const double *w, double *g,
+                          int batch, hipStream_t s)
+{
+    dim3 grid(row_grid(d), batch);
+    if (d.dim == 2) hipLaunchKernelGGL((k_bc_grad<2>), grid, dim3(256), 0, s, d, fwd, lam, w, g);
+    else hipLaunchKernelGGL((k_bc_grad<3>), grid, dim3(256), 0, s, d, fwd, lam, w, g);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+#define TWMG_INST(T)                                                                                                  \
+    template hipError_t launch_block_sweep<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, int, \
+                                              hipStream_t);                                                           \
+    template hipError_t launch_checker<T>(const Dims &, const Coef<T> &, T *, const T *, int, int, hipStream_t);     \
+    template hipError_t launch_residual<T>(const Dims &, const Coef<T> &, const T *, const T *, T *, int,           \
+                                           hipStream_t);                                                              \
+    template hipError_t launch_residual_restrict<T>(const Dims &, const Dims &, const Coef<T> &, const T *,          \
+                                                    const T *, T *, T *, int, hipStream_t);                           \
+    template hipError_t launch_prolong_add<T>(const Dims &, const Dims &, const T *, T *, int, hipStream_t);         \
+    template hipError_t launch_coarse_solve<T>(const Dims &, const Coef<T> &, T *, const T *, const T *, int, int,   \
+                                               hipStream_t);                                                          \
+    template hipError_t launch_resnorm<T>(const Dims &, const Coef<T> &, const T *, const T *, double *, int,        \
+                                          double *, int, hipStream_t);                                                \
+    template hipError_t launch_fill<T>(T *, long long, T, hipStream_t);
+
+TWMG_INST(double)
+TWMG_INST(float)
+
+} // namespace twmg

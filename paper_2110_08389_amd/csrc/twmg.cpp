@@ -1,0 +1,1278 @@
+// Host side of libtwmg: grid hierarchy, coefficients, block tables of the
+// relaxation motifs, the multigrid cycle driver and the C ABI (include/twmg.h).
+#include "sweep_core.h"
+#include "twmg.h"
+#include "twmg_debug.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace twmg;
+
+namespace {
+
+constexpr int MAXLEV = 24;
+constexpr int MAX_COARSE_UNK = 1024;
+
+// ---------------------------------------------------------------------------
+// Geometry (Section 5: eq. tanh, eq. tanh_inv; sinh centre clustering)
+// ---------------------------------------------------------------------------
+int make_coords(int kind, double c, int n, double L, const double *given, std::vector<double> &x)
+{
+    x.assign(n + 1, 0.0);
+    for (int i = 0; i <= n; ++i) {
+        const double s = double(i) / double(n);
+        switch (kind) {
+        case MG_UNIFORM: x[i] = L * s; break;
+        case MG_TANH_WALL:
+            if (!(c > 0)) return MG_EINVAL;
+            x[i] = 0.5 * L * (1.0 + std::tanh(c * (2.0 * s - 1.0)) / std::tanh(c));
+            break;
+        case MG_TANH_CENTRE:
+            if (!(c > 0)) return MG_EINVAL;
+            x[i] = (2 * i <= n) ? 0.5 * L * std::tanh(2.0 * c * s) / std::tanh(c)
+                                : 0.5 * L * (2.0 - std::tanh(c * (2.0 - 2.0 * s)) / std::tanh(c));
+            break;
+        case MG_SINH_CENTRE:
+            if (!(c > 0)) return MG_EINVAL;
+            x[i] = L * (0.5 + std::sinh(c * (2.0 * s - 1.0)) / (2.0 * std::sinh(c)));
+            break;
+        case MG_EXPLICIT:
+            if (!given) return MG_EINVAL;
+            x[i] = given[i];
+            break;
+        default: return MG_EINVAL;
+        }
+    }
+    if (kind != MG_EXPLICIT) {
+        x[0] = 0.0;
+        x[n] = L;
+    }
+    for (int i = 0; i < n; ++i)
+        if (!(x[i + 1] > x[i])) return MG_EINVAL;
+    return MG_OK;
+}
+
+// Section 2: W_i = 1/(dx_i dx_{i-1/2}), E_i = 1/(dx_i dx_{i+1/2}), dx_i = (x_{i+1}-x_{i-1})/2
+void make_coefs(const std::vector<double> &x, std::vector<double> &lo, std::vector<double> &hi)
+{
+    const int n = (int)x.size() - 1;
+    lo.assign(n + 1, 0.0);
+    hi.assign(n + 1, 0.0);
+    for (int i = 1; i < n; ++i) {
+        const double hm = x[i] - x[i - 1], hp = x[i + 1] - x[i], h = 0.5 * (x[i + 1] - x[i - 1]);
+        lo[i] = 1.0 / (h * hm);
+        hi[i] = 1.0 / (h * hp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Relaxation motifs (Section 3; Section 7 for 3D tweed).  A block is a
+// connected set of interior points with one label; colour 0 is relaxed first.
+//   tweed     : label max(i', j') (3D: the two largest of i', j', l'),
+//               i' = min(i, n_x - i); red when the label (sum) is odd (even in 3D)
+//               so that the corners are red.
+//   wireframe : label min(i', j'); red when odd (outermost box red).
+//   zebra     : lines along one axis; the first interior line is red.
+// ---------------------------------------------------------------------------
+enum Motif { M_TWEED = 0, M_WIREFRAME = 1, M_ZX = 3, M_ZY = 4, M_ZZ = 5 };
+
+void motif_label(int motif, int dim, const int *n, int i, int j, int l, long long &lab, int &col)
+{
+    const int ip = std::min(i, n[0] - i), jp = std::min(j, n[1] - j), lp = dim == 3 ? std::min(l, n[2] - l) : 0;
+    switch (motif) {
+    case M_TWEED:
+        if (dim == 2) {
+            const int k = std::max(ip, jp);
+            lab = k;
+            col = (k & 1) ? 0 : 1;
+        } else {
+            int s[3] = {ip, jp, lp};
+            std::sort(s, s + 3);
+            lab = (long long)s[1] * 1000003LL + s[2];
+            col = ((s[1] + s[2]) & 1) ? 1 : 0;
+        }
+        break;
+    case M_WIREFRAME: {
+        const int r = std::min(ip, jp);
+        lab = r;
+        col = (r & 1) ? 0 : 1;
+        break;
+    }
+    case M_ZX:
+        if (dim == 2) { lab = j; col = (j & 1) ? 0 : 1; }
+        else { lab = (long long)j * 1000003LL + l; col = ((j + l) & 1) ? 1 : 0; }
+        break;
+    case M_ZY:
+        if (dim == 2) { lab = i; col = (i & 1) ? 0 : 1; }
+        else { lab = (long long)i * 1000003LL + l; col = ((i + l) & 1) ? 1 : 0; }
+        break;
+    case M_ZZ:
+        lab = (long long)i * 1000003LL + j;
+        col = ((i + j) & 1) ? 1 : 0;
+        break;
+    default: lab = -1; col = 0;
+    }
+}
+
+struct Grid3 {
+    int dim, n[3], np[3];
+    long long st[3], nn;
+    void coords(long long p, int &i, int &j, int &l) const
+    {
+        i = int(p % np[0]);
+        j = int((p / np[0]) % np[1]);
+        l = int(p / ((long long)np[0] * np[1]));
+    }
+    bool interior(int i, int j, int l) const
+    {
+        if (i < 1 || i > n[0] - 1 || j < 1 || j > n[1] - 1) return false;
+        if (dim == 3 && (l < 1 || l > n[2] - 1)) return false;
+        return true;
+    }
+    long long off(int d) const { return (d & 1) ? st[d >> 1] : -st[d >> 1]; }
+};
+
+struct HostBlock {
+    std::vector<Chunk> ch;
+    std::vector<int> succ;     // block-local successor chunk (-1 none, -2 = branch point)
+    int type = BT_CHAIN, m = 0, colour = 0;
+    int ends[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+int find_root(std::vector<int> &par, int x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+// split a straight sequence of points into chunks of at most CH points
+void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, HostBlock &hb)
+{
+    const int n = (int)pts.size();
+    const int first = (int)hb.ch.size();
+    for (int s = 0; s < n; s += CH) {
+        Chunk c;
+        std::memset(&c, 0, sizeof(c));
+        int i, j, l;
+        g.coords(pts[s], i, j, l);
+        c.c0[0] = (int16_t)i;
+        c.c0[1] = (int16_t)j;
+        c.c0[2] = (int16_t)l;
+        c.len = (uint8_t)std::min(CH, n - s);
+        c.axdir = (uint8_t)axdir;
+        c.nextdir = (uint8_t)axdir;
+        const int idx = (int)hb.ch.size();
+        if (s > 0) {
+            c.flags |= CF_PREV;
+            c.prev = (int16_t)(idx - 1);
+        }
+        if (s + CH < n) c.flags |= CF_NEXT;
+        hb.ch.push_back(c);
+        hb.succ.push_back(s + CH < n ? idx + 1 : -1);
+    }
+    (void)first;
+}
+
+
+// Build the block list of one motif on one level (every interior point in
+// exactly one block).  Returns MG_OK or MG_EUNSUPPORTED for shapes the
+// chunked solver does not handle.
+int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
+{
+    const long long nn = g.nn;
+    std::vector<long long> lab(nn, -1);
+    std::vector<int8_t> col(nn, -1);
+    for (long long p = 0; p < nn; ++p) {
+        int i, j, l;
+        g.coords(p, i, j, l);
+        if (!g.interior(i, j, l)) continue;
+        long long lb;
+        int c;
+        motif_label(motif, g.dim, g.n, i, j, l, lb, c);
+        lab[p] = lb;
+        col[p] = (int8_t)c;
+    }
+    std::vector<int> par(nn);
+    std::iota(par.begin(), par.end(), 0);
+    for (long long p = 0; p < nn; ++p) {
+        if (lab[p] < 0) continue;
+        for (int a = 0; a < g.dim; ++a) {
+            const long long q = p + g.st[a];
+            if (q < nn && lab[q] == lab[p]) {
+                int i, j, l;
+                g.coords(q, i, j, l);
+                if (!g.interior(i, j, l)) continue;
+                const int ra = find_root(par, (int)p), rb = find_root(par, (int)q);
+                if (ra != rb) par[std::max(ra, rb)] = std::min(ra, rb);
+            }
+        }
+    }
+    std::vector<int> root(nn, -1);
+    for (long long p = 0; p < nn; ++p)
+        if (lab[p] >= 0) root[p] = find_root(par, (int)p);
+    // in-block neighbour directions of every point
+    std::vector<uint8_t> mask(nn, 0);
+    for (long long p = 0; p < nn; ++p) {
+        if (root[p] < 0) continue;
+        uint8_t m = 0;
+        for (int d = 0; d < 2 * g.dim; ++d) {
+            const long long q = p + g.off(d);
+            if (q < 0 || q >= nn || root[q] != root[p]) continue;
+            int i, j, l;
+            g.coords(q, i, j, l);
+            if (g.interior(i, j, l)) m |= (uint8_t)(1u << d);
+        }
+        mask[p] = m;
+    }
+    // group points by component
+    std::vector<int> cnt(nn + 1, 0);
+    for (long long p = 0; p < nn; ++p)
+        if (root[p] >= 0) cnt[root[p] + 1]++;
+    for (long long p = 0; p < nn; ++p) cnt[p + 1] += cnt[p];
+    std::vector<long long> pts(cnt[nn]);
+    {
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (long long p = 0; p < nn; ++p)
+            if (root[p] >= 0) pts[fill[root[p]]++] = p;
+    }
+    auto deg = [&](long long p) { return __builtin_popcount(mask[p]); };
+    auto is_corner = [&](long long p) {
+        const uint8_t m = mask[p];
+        return __builtin_popcount(m) == 2 && !((m & 3) == 3 || (m & 12) == 12 || (m & 48) == 48);
+    };
+    for (long long r = 0; r < nn; ++r) {
+        const int b = cnt[r], e = cnt[r + 1];
+        if (b == e) continue;
+        const int size = e - b;
+        HostBlock hb;
+        hb.colour = col[pts[b]];
+        long long edges2 = 0;
+        int nbranch = 0;
+        long long branch = -1;
+        for (int k = b; k < e; ++k) {
+            edges2 += deg(pts[k]);
+            if (deg(pts[k]) >= 3) {
+                ++nbranch;
+                branch = pts[k];
+            }
+        }
+        const long long edges = edges2 / 2;
+        if (size == 1) {
+            hb.type = BT_CHAIN;
+            chunk_seq(g, {pts[b]}, 1, hb);
+        } else if (edges == size - 1 && nbranch <= 1) {
+            // tree: a straight line (chain), an L (spider with two legs) or a spider
+            std::vector<std::vector<long long>> legs;
+            std::vector<int> legdir;
+            long long J = -1;
+            if (nbranch == 0) {
+                long long s0 = -1;
+                for (int k = b; k < e; ++k)
+                    if (deg(pts[k]) == 1) { s0 = pts[k]; break; }
+                std::vector<long long> path{s0};
+                std::vector<int> dirs;
+                long long prevp = -1, cur = s0;
+                while (true) {
+                    long long nx = -1;
+                    for (int d = 0; d < 2 * g.dim; ++d)
+                        if ((mask[cur] >> d) & 1) {
+                            const long long q = cur + g.off(d);
+                            if (q != prevp) { nx = q; dirs.push_back(d); break; }
+                        }
+                    if (nx < 0) break;
+                    prevp = cur;
+                    cur = nx;
+                    path.push_back(cur);
+                }
+                if ((int)path.size() != size) return MG_EUNSUPPORTED;
+                std::vector<int> turns;
+                for (size_t k = 1; k < dirs.size(); ++k)
+                    if (dirs[k] != dirs[k - 1]) turns.push_back((int)k);
+                if (turns.empty()) {
+                    hb.type = BT_CHAIN;
+                    chunk_seq(g, path, dirs[0], hb);
+                } else if (turns.size() == 1) {
+                    const int tj = turns[0]; // path[tj] is the turning point
+                    J = path[tj];
+                    legs.push_back(std::vector<long long>(path.begin(), path.begin() + tj));
+                    legdir.push_back(dirs[0]);
+                    std::vector<long long> other(path.rbegin(), path.rend() - tj - 1);
+                    legs.push_back(other);
+                    legdir.push_back(dirs.back() ^ 1);
+                } else {
+                    return MG_EUNSUPPORTED;
+                }
+            } else {
+                J = branch;
+                for (int d = 0; d < 2 * g.dim; ++d) {
+                    if (!((mask[J] >> d) & 1)) continue;
+                    std::vector<long long> walk;
+                    long long cur = J + g.off(d);
+                    while (true) {
+                        walk.push_back(cur);
+                        const uint8_t m = mask[cur];
+                        if (m == (uint8_t)(1u << (d ^ 1))) break;       // tip
+                        if (m != (uint8_t)((1u << d) | (1u << (d ^ 1)))) return MG_EUNSUPPORTED;
+                        cur += g.off(d);
+                    }
+                    std::reverse(walk.begin(), walk.end());
+                    legs.push_back(walk);
+                    legdir.push_back(d ^ 1);
+                }
+            }
+            if (J >= 0) {
+                hb.type = BT_SPIDER;
+                hb.m = (int)legs.size();
+                if (hb.m > 7) return MG_EUNSUPPORTED;
+                uint8_t jmask = 0;
+                for (int lg = 1; lg < hb.m; ++lg) {
+                    chunk_seq(g, legs[lg], legdir[lg], hb);
+                    Chunk &last = hb.ch.back();
+                    last.flags |= CF_NEXT | CF_NEXT_DIRECT;
+                    last.nextdir = (uint8_t)legdir[lg];
+                    hb.succ.back() = -2;
+                    hb.ends[lg] = (int)hb.ch.size() - 1;
+                    jmask |= (uint8_t)(1u << (legdir[lg] ^ 1));
+                }
+                std::vector<long long> l0 = legs[0];
+                l0.push_back(J);
+                chunk_seq(g, l0, legdir[0], hb);
+                hb.ch.back().flags |= CF_JUNCTION;
+                hb.ch.back().jmask = jmask;
+            }
+        } else if (edges == size && nbranch == 0) {
+            // ring: split into straight sides, each ending at a corner
+            long long c0 = -1;
+            for (int k = b; k < e; ++k)
+                if (is_corner(pts[k])) { c0 = pts[k]; break; }
+            if (c0 < 0) return MG_EUNSUPPORTED;
+            int d = __builtin_ctz(mask[c0]);
+            std::vector<std::vector<long long>> sides;
+            std::vector<int> sdir;
+            std::vector<long long> cur_side;
+            long long cur = c0;
+            int visited = 0;
+            while (true) {
+                cur += g.off(d);
+                cur_side.push_back(cur);
+                ++visited;
+                if (visited > size) return MG_EUNSUPPORTED;
+                const uint8_t m = mask[cur];
+                if (is_corner(cur)) {
+                    sides.push_back(cur_side);
+                    sdir.push_back(d);
+                    cur_side.clear();
+                    const int back = d ^ 1;
+                    d = __builtin_ctz((uint8_t)(m & ~(1u << back)));
+                    if (cur == c0) break;
+                } else if (m != (uint8_t)((1u << d) | (1u << (d ^ 1)))) {
+                    return MG_EUNSUPPORTED;
+                }
+            }
+            if (visited != size) return MG_EUNSUPPORTED;
+            hb.type = BT_RING;
+            std::vector<int> firsts;
+            for (size_t s = 0; s < sides.size(); ++s) {
+                firsts.push_back((int)hb.ch.size());
+                chunk_seq(g, sides[s], sdir[s], hb);
+                Chunk &last = hb.ch.back();
+                last.flags |= CF_NEXT;
+                last.nextdir = (uint8_t)sdir[(s + 1) % sides.size()];
+                hb.succ.back() = -3 - (int)((s + 1) % sides.size()); // patched below
+            }
+            const int nc = (int)hb.ch.size();
+            for (size_t s = 0; s < sides.size(); ++s) {
+                Chunk &f0 = hb.ch[firsts[s]];
+                f0.flags |= CF_PREV;
+                f0.prev = (int16_t)((firsts[s] - 1 + nc) % nc);
+            }
+            for (int k = 0; k < nc; ++k)
+                if (hb.succ[k] <= -3) hb.succ[k] = firsts[-3 - hb.succ[k]];
+        } else {
+            return MG_EUNSUPPORTED;
+        }
+        // successor links: direct when the successor chunk has no interior
+        for (size_t k = 0; k < hb.ch.size(); ++k) {
+            const int sc = hb.succ[k];
+            if (sc >= 0 && hb.ch[sc].len == 1) hb.ch[k].flags |= CF_NEXT_DIRECT;
+        }
+        if ((int)hb.ch.size() > NT) return MG_EUNSUPPORTED;
+        out.push_back(std::move(hb));
+    }
+    return MG_OK;
+}
+
+// Pack the blocks of one colour into workgroups (largest blocks first so the
+// longest reduced solves start early).
+struct HostTable {
+    std::vector<Chunk> chunks;
+    std::vector<Block> blocks;
+    std::vector<WGDesc> wgs;
+};
+
+void pack(std::vector<const HostBlock *> bl, HostTable &t)
+{
+    std::stable_sort(bl.begin(), bl.end(),
+                     [](const HostBlock *a, const HostBlock *b) { return a->ch.size() > b->ch.size(); });
+    WGDesc cur{0, 0, 0, 0};
+    auto flush = [&]() {
+        if (cur.nchunk) t.wgs.push_back(cur);
+        cur = WGDesc{(int)t.chunks.size(), 0, (int)t.blocks.size(), 0};
+    };
+    flush();
+    for (const HostBlock *hb : bl) {
+        const int nc = (int)hb->ch.size();
+        if (cur.nchunk + nc > NT || cur.nblock + 1 > NT) flush();
+        const int o = cur.nchunk;
+        for (Chunk c : hb->ch) {
+            if (c.flags & CF_PREV) c.prev = (int16_t)(c.prev + o);
+            t.chunks.push_back(c);
+        }
+        Block bk;
+        std::memset(&bk, 0, sizeof(bk));
+        bk.first = (int16_t)o;
+        bk.count = (int16_t)nc;
+        bk.type = (uint8_t)hb->type;
+        bk.m = (uint8_t)hb->m;
+        for (int k = 0; k < 7; ++k) bk.ends[k] = (int16_t)(hb->ends[k] + o);
+        t.blocks.push_back(bk);
+        cur.nchunk += nc;
+        cur.nblock += 1;
+    }
+    flush();
+}
+
+// Bounds check of a table against its grid before it is uploaded: every
+// chunk point and every in-block neighbour it names is an interior node, and
+// every workgroup-local index stays inside its workgroup.
+bool validate(const Grid3 &g, const HostTable &t)
+{
+    const int nc = (int)t.chunks.size(), nb = (int)t.blocks.size();
+    for (const WGDesc &w : t.wgs) {
+        if (w.chunk0 < 0 || w.nchunk < 1 || w.nchunk > NT || w.chunk0 + w.nchunk > nc) return false;
+        if (w.block0 < 0 || w.nblock < 1 || w.nblock > NT || w.block0 + w.nblock > nb) return false;
+        for (int k = 0; k < w.nchunk; ++k) {
+            const Chunk &c = t.chunks[w.chunk0 + k];
+            if (c.len < 1 || c.len > CH || c.axdir >= 2 * g.dim || c.nextdir >= 2 * g.dim) return false;
+            if ((c.flags & CF_PREV) && (c.prev < 0 || c.prev >= w.nchunk)) return false;
+            const int ax = c.axdir >> 1, sg = (c.axdir & 1) ? 1 : -1;
+            int p[3] = {c.c0[0], c.c0[1], g.dim == 3 ? c.c0[2] : 0};
+            p[ax] -= sg;
+            for (int q = 0; q <= c.len; ++q) {
+                // q = 0 is the predecessor position (interior, or the boundary node a tip faces)
+                if (q > 0 && !g.interior(p[0], p[1], p[2])) return false;
+                for (int a = 0; a < g.dim; ++a)
+                    if (p[a] < 0 || p[a] > g.n[a]) return false;
+                if (q < c.len) p[ax] += sg;
+            }
+            // p is now the last point
+            if (c.flags & CF_NEXT) {
+                int s[3] = {p[0], p[1], p[2]};
+                s[c.nextdir >> 1] += (c.nextdir & 1) ? 1 : -1;
+                if (!g.interior(s[0], s[1], s[2])) return false;
+            }
+            if (c.flags & CF_JUNCTION)
+                for (int d = 0; d < 2 * g.dim; ++d)
+                    if ((c.jmask >> d) & 1) {
+                        int s[3] = {p[0], p[1], p[2]};
+                        s[d >> 1] += (d & 1) ? 1 : -1;
+                        if (!g.interior(s[0], s[1], s[2])) return false;
+                    }
+        }
+        for (int k = 0; k < w.nblock; ++k) {
+            const Block &b = t.blocks[w.block0 + k];
+            if (b.first < 0 || b.count < 1 || b.first + b.count > w.nchunk || b.type > BT_RING || b.m > 7) return false;
+            if (b.type == BT_SPIDER)
+                for (int l = 1; l < b.m; ++l)
+                    if (b.ends[l] < b.first || b.ends[l] >= b.first + b.count - 1) return false;
+            if (b.type == BT_RING && b.count < 3) return false;
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+struct DevPool {
+    std::vector<void *> owned;
+    bool host_only = false; // build host-side structures only (test hook, no device calls)
+    ~DevPool()
+    {
+        for (void *p : owned) (void)hipFree(p);
+    }
+    template <typename T> T *upload(const std::vector<T> &v, int &err)
+    {
+        if (v.empty() || host_only) return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) {
+            err = MG_ENOMEM;
+            return nullptr;
+        }
+        owned.push_back(p);
+        if (hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) err = MG_EHIP;
+        return (T *)p;
+    }
+};
+
+struct Level {
+    Dims d;
+    Grid3 g;
+    std::vector<double> x[3], lo[3], hi[3];
+    Coef<double> c64[2];  // [forward, transposed]
+    Coef<float> c32[2];
+    SweepTable tab[2][2]; // [motif slot][colour]
+    HostTable htab[2][2]; // host copies (validation and the host emulation hook)
+    std::vector<double> hco[2][3][3]; // [fwd/transposed][lo,hi,dg][axis]
+    Coef<double> hc64[2];
+    double *u = nullptr, *f = nullptr;   // FP64 work arrays (levels >= 1)
+    float *u32 = nullptr, *f32 = nullptr; // FP32 work arrays (all levels)
+};
+
+} // namespace
+
+struct mg_handle {
+    mg_grid grid;
+    mg_options opt;
+    hipStream_t stream = nullptr;
+    int nlev = 0;
+    Level lev[MAXLEV];
+    int slot_motif[2] = {-1, -1};
+    bool checker = false;
+    int nunk_coarse = 0;
+    double *cinv64[2] = {nullptr, nullptr};
+    float *cinv32[2] = {nullptr, nullptr};
+    double *partial = nullptr, *normv = nullptr;
+    double *h_norm = nullptr;  // pinned
+    DevPool pool;
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    bool ws_owned = false;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                                                     \
+    do {                                                                                                              \
+        if ((x) != hipSuccess) return MG_EHIP;                                                                        \
+    } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t workspace_layout(mg_handle *h, bool assign)
+{
+    size_t off = 0;
+    const int B = h->grid.batch;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    for (int l = 0; l < h->nlev; ++l) {
+        Level &L = h->lev[l];
+        const size_t n = (size_t)L.d.nn * B;
+        size_t ou = 0, of = 0;
+        if (l > 0) {
+            ou = take(n * sizeof(double));
+            of = take(n * sizeof(double));
+        }
+        const size_t ou32 = take(n * sizeof(float)), of32 = take(n * sizeof(float));
+        if (assign) {
+            if (l > 0) {
+                L.u = (double *)(h->ws + ou);
+                L.f = (double *)(h->ws + of);
+            }
+            L.u32 = (float *)(h->ws + ou32);
+            L.f32 = (float *)(h->ws + of32);
+        }
+    }
+    return off;
+}
+
+int clear_workspace(mg_handle *h)
+{
+    // coarse arrays start at zero: their boundary entries are never written
+    for (int l = 0; l < h->nlev; ++l) {
+        Level &L = h->lev[l];
+        const long long n = L.d.nn * h->grid.batch;
+        if (l > 0) {
+            HIPCHK(launch_fill<double>(L.u, n, 0.0, h->stream));
+            HIPCHK(launch_fill<double>(L.f, n, 0.0, h->stream));
+        }
+        HIPCHK(launch_fill<float>(L.u32, n, 0.0f, h->stream));
+        HIPCHK(launch_fill<float>(L.f32, n, 0.0f, h->stream));
+    }
+    return MG_OK;
+}
+
+int ensure_workspace(mg_handle *h)
+{
+    if (h->ws) return MG_OK;
+    void *p = nullptr;
+    if (hipMalloc(&p, h->ws_bytes) != hipSuccess) return MG_ENOMEM;
+    h->ws = (char *)p;
+    h->ws_owned = true;
+    workspace_layout(h, true);
+    return clear_workspace(h);
+}
+
+// dense inverse of the coarsest interior operator (Gauss-Jordan, partial pivoting)
+bool invert(std::vector<double> &A, int n, std::vector<double> &inv)
+{
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = i;
+        if (A[(size_t)piv * n + k] == 0.0) return false;
+        if (piv != k)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+                std::swap(inv[(size_t)k * n + j], inv[(size_t)piv * n + j]);
+            }
+        const double dinv = 1.0 / A[(size_t)k * n + k];
+        for (int j = 0; j < n; ++j) {
+            A[(size_t)k * n + j] *= dinv;
+            inv[(size_t)k * n + j] *= dinv;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double fct = A[(size_t)i * n + k];
+            if (fct == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[(size_t)i * n + j] -= fct * A[(size_t)k * n + j];
+                inv[(size_t)i * n + j] -= fct * inv[(size_t)k * n + j];
+            }
+        }
+    }
+    return true;
+}
+
+int motif_slots(int smoother, int dim, int *m0, int *m1, bool *checker)
+{
+    *m0 = *m1 = -1;
+    *checker = false;
+    switch (smoother) {
+    case MG_TWEED: *m0 = M_TWEED; break;
+    case MG_WIREFRAME:
+        if (dim != 2) return MG_EUNSUPPORTED;
+        *m0 = M_WIREFRAME;
+        break;
+    case MG_CHECKERBOARD: *checker = true; break;
+    case MG_ZEBRA_X: *m0 = M_ZX; break;
+    case MG_ZEBRA_Y: *m0 = M_ZY; break;
+    case MG_ZEBRA_Z:
+        if (dim != 3) return MG_EINVAL;
+        *m0 = M_ZZ;
+        break;
+    case MG_ADZ:
+        *m0 = M_ZX;
+        *m1 = M_ZY;
+        if (dim == 3) return MG_EUNSUPPORTED; // three-direction variant not provided
+        break;
+    case MG_ALT_TW:
+        if (dim != 2) return MG_EUNSUPPORTED;
+        *m0 = M_TWEED;
+        *m1 = M_WIREFRAME;
+        break;
+    default: return MG_EINVAL;
+    }
+    return MG_OK;
+}
+
+int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const mg_options *opt)
+{
+    if (grid->dim != 2 && grid->dim != 3) return MG_EINVAL;
+    if (grid->batch < 1) return MG_EINVAL;
+    for (int a = 0; a < grid->dim; ++a) {
+        if (grid->n[a] < 2 || grid->n[a] % 2 || grid->n[a] > 32000) return MG_EINVAL;
+        if (!(grid->L[a] > 0)) return MG_EINVAL;
+    }
+    if (opt->nu1 < 0 || opt->nu2 < 0 || opt->gamma < 1 || opt->gamma > 2 || opt->max_cycles < 1) return MG_EINVAL;
+    if (opt->precision != MG_FP64 && opt->precision != MG_FP32_IR) return MG_EINVAL;
+    h->grid = *grid;
+    h->opt = *opt;
+    int rc = motif_slots(opt->smoother, grid->dim, &h->slot_motif[0], &h->slot_motif[1], &h->checker);
+    if (rc) return rc;
+    const int dim = grid->dim;
+    // finest coordinates
+    std::vector<double> x0[3];
+    for (int a = 0; a < dim; ++a) {
+        rc = make_coords(st->kind[a], st->param[a], grid->n[a], grid->L[a], st->coords[a], x0[a]);
+        if (rc) return rc;
+    }
+    // hierarchy (Section 4): coarse nodes are every other fine node; stop when an
+    // axis has an odd number of cells or only two
+    int cur[3] = {grid->n[0], grid->n[1], dim == 3 ? grid->n[2] : 0};
+    int nl = 0;
+    while (true) {
+        Level &L = h->lev[nl];
+        L.d.dim = dim;
+        L.g.dim = dim;
+        for (int a = 0; a < 3; ++a) {
+            L.d.n[a] = a < dim ? cur[a] : 0;
+            L.g.n[a] = L.d.n[a];
+            L.g.np[a] = a < dim ? cur[a] + 1 : 1;
+        }
+        L.d.st[0] = 1;
+        L.d.st[1] = L.g.np[0];
+        L.d.st[2] = dim == 3 ? (long long)L.g.np[0] * L.g.np[1] : 0;
+        L.d.nn = (long long)L.g.np[0] * L.g.np[1] * L.g.np[2];
+        for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
+        L.g.nn = L.d.nn;
+        for (int a = 0; a < dim; ++a) {
+            if (nl == 0) L.x[a] = x0[a];
+            else {
+                L.x[a].resize(cur[a] + 1);
+                for (int i = 0; i <= cur[a]; ++i) L.x[a][i] = h->lev[nl - 1].x[a][2 * i];
+            }
+            make_coefs(L.x[a], L.lo[a], L.hi[a]);
+        }
+        ++nl;
+        bool can = true;
+        for (int a = 0; a < dim; ++a)
+            if (cur[a] % 2 || cur[a] < 4) can = false;
+        if (!can || nl >= MAXLEV) break;
+        for (int a = 0; a < dim; ++a) cur[a] /= 2;
+    }
+    h->nlev = nl;
+    // coefficient arrays: forward and transposed, FP64 and FP32
+    for (int l = 0; l < nl; ++l) {
+        Level &L = h->lev[l];
+        for (int a = 0; a < 3; ++a) {
+            const int n = a < dim ? L.d.n[a] : 0;
+            std::vector<double> lo(n + 1, 0.0), hi(n + 1, 0.0), dg(n + 1, 0.0), loT(n + 1, 0.0), hiT(n + 1, 0.0);
+            if (a < dim) {
+                lo = L.lo[a];
+                hi = L.hi[a];
+                for (int i = 1; i < n; ++i) {
+                    dg[i] = -(lo[i] + hi[i]);
+                    loT[i] = (i - 1 >= 1) ? hi[i - 1] : 0.0;
+                    hiT[i] = (i + 1 <= n - 1) ? lo[i + 1] : 0.0;
+                }
+            }
+            L.hco[0][0][a] = lo;
+            L.hco[0][1][a] = hi;
+            L.hco[0][2][a] = dg;
+            L.hco[1][0][a] = loT;
+            L.hco[1][1][a] = hiT;
+            L.hco[1][2][a] = dg;
+            std::vector<float> lo32(lo.begin(), lo.end()), hi32(hi.begin(), hi.end()), dg32(dg.begin(), dg.end()),
+                loT32(loT.begin(), loT.end()), hiT32(hiT.begin(), hiT.end());
+            int err = 0;
+            L.c64[0].lo[a] = h->pool.upload(lo, err);
+            L.c64[0].hi[a] = h->pool.upload(hi, err);
+            L.c64[0].dg[a] = h->pool.upload(dg, err);
+            L.c64[1].lo[a] = h->pool.upload(loT, err);
+            L.c64[1].hi[a] = h->pool.upload(hiT, err);
+            L.c64[1].dg[a] = L.c64[0].dg[a];
+            L.c32[0].lo[a] = h->pool.upload(lo32, err);
+            L.c32[0].hi[a] = h->pool.upload(hi32, err);
+            L.c32[0].dg[a] = h->pool.upload(dg32, err);
+            L.c32[1].lo[a] = h->pool.upload(loT32, err);
+            L.c32[1].hi[a] = h->pool.upload(hiT32, err);
+            L.c32[1].dg[a] = L.c32[0].dg[a];
+            if (err) return err;
+        }
+    }
+    for (int l = 0; l < nl; ++l)
+        for (int o = 0; o < 2; ++o)
+            for (int a = 0; a < 3; ++a) {
+                h->lev[l].hc64[o].lo[a] = h->lev[l].hco[o][0][a].data();
+                h->lev[l].hc64[o].hi[a] = h->lev[l].hco[o][1][a].data();
+                h->lev[l].hc64[o].dg[a] = h->lev[l].hco[o][2][a].data();
+            }
+    // block tables for every level that is smoothed
+    for (int l = 0; l + 1 < nl; ++l) {
+        Level &L = h->lev[l];
+        for (int s = 0; s < 2; ++s) {
+            if (h->slot_motif[s] < 0) continue;
+            std::vector<HostBlock> blocks;
+            rc = build_blocks(L.g, h->slot_motif[s], blocks);
+            if (rc) return rc;
+            for (int colour = 0; colour < 2; ++colour) {
+                std::vector<const HostBlock *> sel;
+                for (const HostBlock &hb : blocks)
+                    if (hb.colour == colour) sel.push_back(&hb);
+                HostTable &t = L.htab[s][colour];
+                pack(sel, t);
+                if (!validate(L.g, t)) return MG_EUNSUPPORTED;
+                int err = 0;
+                SweepTable &T = L.tab[s][colour];
+                T.chunks = h->pool.upload(t.chunks, err);
+                T.blocks = h->pool.upload(t.blocks, err);
+                T.wgs = h->pool.upload(t.wgs, err);
+                T.nwg = (int)t.wgs.size();
+                T.nchunk = (int)t.chunks.size();
+                T.nblock = (int)t.blocks.size();
+                if (err) return err;
+            }
+        }
+    }
+    // coarsest direct solve
+    {
+        Level &C = h->lev[nl - 1];
+        const int nx = C.d.n[0] - 1, ny = C.d.n[1] - 1, nz = dim == 3 ? C.d.n[2] - 1 : 1;
+        const int nu = nx * ny * nz;
+        if (nu > MAX_COARSE_UNK) return MG_EUNSUPPORTED;
+        h->nunk_coarse = nu;
+        std::vector<double> A((size_t)nu * nu, 0.0);
+        for (int q = 0; q < nu; ++q) {
+            const int c[3] = {1 + q % nx, 1 + (q / nx) % ny, dim == 3 ? 1 + q / (nx * ny) : 0};
+            double dg = 0;
+            for (int a = 0; a < dim; ++a) dg -= C.lo[a][c[a]] + C.hi[a][c[a]];
+            A[(size_t)q * nu + q] = dg;
+            const int sz[3] = {1, nx, nx * ny};
+            const int lim[3] = {nx, ny, nz};
+            for (int a = 0; a < dim; ++a) {
+                if (c[a] > 1) A[(size_t)q * nu + q - sz[a]] = C.lo[a][c[a]];
+                if (c[a] < lim[a]) A[(size_t)q * nu + q + sz[a]] = C.hi[a][c[a]];
+            }
+        }
+        std::vector<double> At((size_t)nu * nu);
+        for (int i = 0; i < nu; ++i)
+            for (int j = 0; j < nu; ++j) At[(size_t)i * nu + j] = A[(size_t)j * nu + i];
+        std::vector<double> inv, invT;
+        if (!invert(A, nu, inv) || !invert(At, nu, invT)) return MG_EINVAL;
+        std::vector<float> inv32(inv.begin(), inv.end()), invT32(invT.begin(), invT.end());
+        int err = 0;
+        h->cinv64[0] = h->pool.upload(inv, err);
+        h->cinv64[1] = h->pool.upload(invT, err);
+        h->cinv32[0] = h->pool.upload(inv32, err);
+        h->cinv32[1] = h->pool.upload(invT32, err);
+        if (err) return err;
+    }
+    {
+        std::vector<double> z(NORM_PARTS + 1, 0.0);
+        int err = 0;
+        h->partial = h->pool.upload(z, err);
+        h->normv = h->partial + NORM_PARTS;
+        if (err) return err;
+        if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double)));
+    }
+    h->ws_bytes = workspace_layout(h, false);
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// cycle driver (Section 4, steps (1)-(6))
+// ---------------------------------------------------------------------------
+template <typename T> const Coef<T> &coefs(const Level &L, int adj);
+template <> const Coef<double> &coefs<double>(const Level &L, int adj) { return L.c64[adj]; }
+template <> const Coef<float> &coefs<float>(const Level &L, int adj) { return L.c32[adj]; }
+template <typename T> T *lev_u(Level &L);
+template <typename T> T *lev_f(Level &L);
+template <> double *lev_u<double>(Level &L) { return L.u; }
+template <> double *lev_f<double>(Level &L) { return L.f; }
+template <> float *lev_u<float>(Level &L) { return L.u32; }
+template <> float *lev_f<float>(Level &L) { return L.f32; }
+template <typename T> const T *cinv(const mg_handle *h, int adj);
+template <> const double *cinv<double>(const mg_handle *h, int adj) { return h->cinv64[adj]; }
+template <> const float *cinv<float>(const mg_handle *h, int adj) { return h->cinv32[adj]; }
+
+// one relaxation (for the alternating schemes: the group of sweeps); the
+// adjoint runs sweeps and colours in reverse order
+template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
+{
+    Level &L = h->lev[lv];
+    const Coef<T> &c = coefs<T>(L, adj);
+    const int B = h->grid.batch;
+    if (h->checker) {
+        for (int k = 0; k < 2; ++k) HIPCHK(launch_checker<T>(L.d, c, u, f, adj ? 1 - k : k, B, h->stream));
+        return MG_OK;
+    }
+    const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+    for (int k = 0; k < ns; ++k) {
+        const int s = adj ? ns - 1 - k : k;
+        for (int q = 0; q < 2; ++q) {
+            const int colour = adj ? 1 - q : q;
+            HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], B, h->stream));
+        }
+    }
+    return MG_OK;
+}
+
+template <typename T> int cycle(mg_handle *h, int lv, T *u, const T *f, int adj)
+{
+    Level &L = h->lev[lv];
+    const int B = h->grid.batch;
+    if (lv == h->nlev - 1) {
+        HIPCHK(launch_coarse_solve<T>(L.d, coefs<T>(L, adj), u, f, cinv<T>(h, adj), h->nunk_coarse, B, h->stream));
+        return MG_OK;
+    }
+    int rc;
+    for (int s = 0; s < h->opt.nu1; ++s)
+        if ((rc = relax<T>(h, lv, u, f, adj))) return rc;
+    Level &C = h->lev[lv + 1];
+    T *uc = lev_u<T>(C), *fc = lev_f<T>(C);
+    HIPCHK(launch_residual_restrict<T>(L.d, C.d, coefs<T>(L, adj), u, f, fc, uc, B, h->stream));
+    for (int g = 0; g < h->opt.gamma; ++g)
+        if ((rc = cycle<T>(h, lv + 1, uc, fc, adj))) return rc;
+    HIPCHK(launch_prolong_add<T>(L.d, C.d, uc, u, B, h->stream));
+    for (int s = 0; s < h->opt.nu2; ++s)
+        if ((rc = relax<T>(h, lv, u, f, adj))) return rc;
+    return MG_OK;
+}
+
+int read_norm(mg_handle *h, double *out)
+{
+    HIPCHK(hipMemcpyAsync(h->h_norm, h->normv, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *out = *h->h_norm;
+    return MG_OK;
+}
+
+int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *stats, int adj)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
+    Level &L = h->lev[0];
+    const int B = h->grid.batch;
+    const bool ir = h->opt.precision == MG_FP32_IR;
+    double d0 = 0, d = 0;
+    HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
+    if ((rc = read_norm(h, &d0))) return rc;
+    int k = 0, status = MG_OK;
+    double rel = 0.0;
+    if (!(d0 == d0) || std::isinf(d0)) status = MG_EDIVERGED;
+    else if (d0 > 0.0) {
+        status = MG_ENOTCONV;
+        while (k < h->opt.max_cycles) {
+            if (ir) {
+                // r = f - A u (FP64) rounded to FP32; e = FP32 cycle on A e = r from 0; u += e
+                HIPCHK(launch_resnorm_to_f32(L.d, L.c64[adj], u, f, L.f32, h->partial, NORM_PARTS, h->normv, B,
+                                             h->stream));
+                HIPCHK(launch_fill<float>(L.u32, L.d.nn * B, 0.0f, h->stream));
+                if ((rc = cycle<float>(h, 0, L.u32, L.f32, adj))) return rc;
+                HIPCHK(launch_ir_update(L.d, u, L.u32, B, h->stream));
+            } else {
+                if ((rc = cycle<double>(h, 0, u, f, adj))) return rc;
+            }
+            HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
+            if ((rc = read_norm(h, &d))) return rc;
+            rel = d / d0;
+            if (stats && stats->history && k < stats->history_cap) stats->history[k] = rel;
+            ++k;
+            if (!(rel == rel) || std::isinf(rel) || rel > 1e6) {
+                status = MG_EDIVERGED;
+                break;
+            }
+            if (rel < tol) {
+                status = MG_OK;
+                break;
+            }
+        }
+    }
+    if (stats) {
+        stats->cycles = k;
+        stats->status = status;
+        stats->rel_res = rel;
+        stats->res0 = d0;
+        stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+bool bad_level(const mg_handle *h, int lv) { return !h || lv < 0 || lv >= h->nlev; }
+
+} // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int mg_setup(const mg_grid *grid, const mg_stretching *stretch, const mg_options *opt, void *stream, mg_handle **out)
+{
+    if (!grid || !stretch || !opt || !out) return MG_EINVAL;
+    mg_handle *h = new (std::nothrow) mg_handle();
+    if (!h) return MG_ENOMEM;
+    h->stream = (hipStream_t)stream;
+    int rc;
+    try {
+        rc = setup_impl(h, grid, stretch, opt);
+    } catch (const std::bad_alloc &) {
+        rc = MG_ENOMEM;
+    } catch (...) {
+        rc = MG_EINVAL;
+    }
+    if (rc) {
+        mg_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return MG_OK;
+}
+
+void mg_destroy(mg_handle *h)
+{
+    if (!h) return;
+    if (h->pool.host_only) {
+        delete h;
+        return;
+    }
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+    if (h->h_norm) (void)hipHostFree(h->h_norm);
+    delete h;
+}
+
+int mg_set_stream(mg_handle *h, void *stream)
+{
+    if (!h) return MG_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return MG_OK;
+}
+
+int mg_set_options(mg_handle *h, const mg_options *opt)
+{
+    if (!h || !opt) return MG_EINVAL;
+    if (opt->nu1 < 0 || opt->nu2 < 0 || opt->gamma < 1 || opt->gamma > 2 || opt->max_cycles < 1) return MG_EINVAL;
+    if (opt->precision != MG_FP64 && opt->precision != MG_FP32_IR) return MG_EINVAL;
+    int m0, m1;
+    bool ck;
+    const int rc = motif_slots(opt->smoother, h->grid.dim, &m0, &m1, &ck);
+    if (rc) return rc;
+    if (!ck && (m0 != h->slot_motif[0] || m1 != h->slot_motif[1])) return MG_EINVAL;
+    h->opt = *opt;
+    h->checker = ck;
+    return MG_OK;
+}
+
+size_t mg_workspace_bytes(const mg_handle *h) { return h ? h->ws_bytes : 0; }
+
+int mg_bind_workspace(mg_handle *h, void *dev_ptr, size_t bytes)
+{
+    if (!h || !dev_ptr || ((uintptr_t)dev_ptr & 255)) return MG_EINVAL;
+    if (bytes < h->ws_bytes) return MG_ENOMEM;
+    if (h->ws_owned && h->ws) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->ws);
+    }
+    h->ws = (char *)dev_ptr;
+    h->ws_owned = false;
+    workspace_layout(h, true);
+    return clear_workspace(h);
+}
+
+int mg_levels(const mg_handle *h, int *nlevels)
+{
+    if (!h || !nlevels) return MG_EINVAL;
+    *nlevels = h->nlev;
+    return MG_OK;
+}
+
+int mg_level_shape(const mg_handle *h, int lv, int *n)
+{
+    if (bad_level(h, lv) || !n) return MG_EINVAL;
+    for (int a = 0; a < 3; ++a) n[a] = h->lev[lv].d.n[a];
+    return MG_OK;
+}
+
+int mg_level_coefs(const mg_handle *h, int lv, int axis, double *x, double *lo, double *hi)
+{
+    if (bad_level(h, lv) || axis < 0 || axis >= h->grid.dim) return MG_EINVAL;
+    const Level &L = h->lev[lv];
+    const size_t n = L.x[axis].size();
+    if (x) std::memcpy(x, L.x[axis].data(), n * sizeof(double));
+    if (lo) std::memcpy(lo, L.lo[axis].data(), n * sizeof(double));
+    if (hi) std::memcpy(hi, L.hi[axis].data(), n * sizeof(double));
+    return MG_OK;
+}
+
+int mg_vcycle(mg_handle *h, double *u, const double *f)
+{
+    if (!h || !u || !f) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
+    return cycle<double>(h, 0, u, f, 0);
+}
+
+int mg_solve(mg_handle *h, double *u, const double *f, const double *bc, double tol, mg_stats *stats)
+{
+    if (!h || !u || !f || !(tol >= 0)) return MG_EINVAL;
+    Level &L = h->lev[0];
+    const bool zero = !(h->opt.flags & MG_INITIAL_GUESS);
+    if (bc || zero) HIPCHK(launch_set_boundary(L.d, u, bc, zero ? 1 : 0, h->grid.batch, h->stream));
+    return solve_impl(h, u, f, tol, stats, 0);
+}
+
+int mg_solve_adjoint(mg_handle *h, double *lam, const double *w, double tol, mg_stats *stats)
+{
+    if (!h || !lam || !w || !(tol >= 0)) return MG_EINVAL;
+    Level &L = h->lev[0];
+    HIPCHK(launch_fill<double>(lam, L.d.nn * h->grid.batch, 0.0, h->stream));
+    return solve_impl(h, lam, w, tol, stats, 1);
+}
+
+int mg_bc_grad(mg_handle *h, const double *lam, const double *w, double *grad_bc)
+{
+    if (!h || !lam || !w || !grad_bc) return MG_EINVAL;
+    Level &L = h->lev[0];
+    HIPCHK(launch_bc_grad(L.d, L.c64[0], lam, w, grad_bc, h->grid.batch, h->stream));
+    return MG_OK;
+}
+
+int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out_inf)
+{
+    if (!h || !u || !f || !out_inf) return MG_EINVAL;
+    Level &L = h->lev[0];
+    HIPCHK(launch_resnorm<double>(L.d, L.c64[0], u, f, h->partial, NORM_PARTS, h->normv, h->grid.batch, h->stream));
+    return read_norm(h, out_inf);
+}
+
+int mg_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
+    for (int s = 0; s < nu; ++s) {
+        const int rc = relax<double>(h, lv, u, f, adjoint ? 1 : 0);
+        if (rc) return rc;
+    }
+    return MG_OK;
+}
+
+int mg_smooth_f32(mg_handle *h, int lv, float *u, const float *f, int nu, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
+    for (int s = 0; s < nu; ++s) {
+        const int rc = relax<float>(h, lv, u, f, adjoint ? 1 : 0);
+        if (rc) return rc;
+    }
+    return MG_OK;
+}
+
+int mg_residual(mg_handle *h, int lv, const double *u, const double *f, double *d, int adjoint)
+{
+    if (bad_level(h, lv) || !u || !f || !d) return MG_EINVAL;
+    Level &L = h->lev[lv];
+    HIPCHK(launch_residual<double>(L.d, L.c64[adjoint ? 1 : 0], u, f, d, h->grid.batch, h->stream));
+    return MG_OK;
+}
+
+int mg_residual_restrict(mg_handle *h, int lv, const double *u, const double *f, double *fc, double *uc, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || !fc || !uc) return MG_EINVAL;
+    Level &L = h->lev[lv], &C = h->lev[lv + 1];
+    HIPCHK(launch_residual_restrict<double>(L.d, C.d, L.c64[adjoint ? 1 : 0], u, f, fc, uc, h->grid.batch,
+                                            h->stream));
+    return MG_OK;
+}
+
+int mg_prolong_add(mg_handle *h, int lv, const double *ec, double *u)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !ec || !u) return MG_EINVAL;
+    Level &L = h->lev[lv], &C = h->lev[lv + 1];
+    HIPCHK(launch_prolong_add<double>(L.d, C.d, ec, u, h->grid.batch, h->stream));
+    return MG_OK;
+}
+
+const char *mg_strerror(int code)
+{
+    switch (code) {
+    case MG_OK: return "ok";
+    case MG_EINVAL: return "invalid argument";
+    case MG_ENOMEM: return "out of memory (or workspace too small)";
+    case MG_EHIP: return "HIP runtime error";
+    case MG_ENOTCONV: return "not converged within max_cycles";
+    case MG_EDIVERGED: return "diverged (NaN/Inf or defect growth)";
+    case MG_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks (include/twmg_debug.h).  Never called by the solver.
+// ---------------------------------------------------------------------------
+int mg_debug_table_info(const mg_handle *h, int lv, int slot, int colour, int *info)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || slot < 0 || slot > 1 || colour < 0 || colour > 1 || !info)
+        return MG_EINVAL;
+    const HostTable &t = h->lev[lv].htab[slot][colour];
+    int maxc = 0, maxb = 0;
+    for (const WGDesc &w : t.wgs) {
+        maxc = std::max(maxc, w.nchunk);
+        maxb = std::max(maxb, w.nblock);
+    }
+    long long pts = 0;
+    for (const Chunk &c : t.chunks) pts += c.len;
+    info[0] = (int)t.wgs.size();
+    info[1] = (int)t.chunks.size();
+    info[2] = (int)t.blocks.size();
+    info[3] = maxc;
+    info[4] = maxb;
+    info[5] = (int)pts;
+    return MG_OK;
+}
+
+int mg_debug_setup_host(const mg_grid *grid, const mg_stretching *stretch, const mg_options *opt, mg_handle **out)
+{
+    if (!grid || !stretch || !opt || !out) return MG_EINVAL;
+    mg_handle *h = new (std::nothrow) mg_handle();
+    if (!h) return MG_ENOMEM;
+    h->pool.host_only = true;
+    int rc;
+    try {
+        rc = setup_impl(h, grid, stretch, opt);
+    } catch (const std::bad_alloc &) {
+        rc = MG_ENOMEM;
+    }
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return MG_OK;
+}
+
+int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
+    if (h->checker) return MG_EUNSUPPORTED;
+    Level &L = h->lev[lv];
+    const int adj = adjoint ? 1 : 0;
+    const Coef<double> &c = L.hc64[adj];
+    std::vector<double> red(8 * NT);
+    RedArrays<double> r{&red[0], &red[NT], &red[2 * NT], &red[3 * NT], &red[4 * NT], &red[5 * NT], &red[6 * NT],
+                        &red[7 * NT]};
+    std::vector<LaneState<double>> st(NT);
+    const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+    for (int it = 0; it < nu; ++it)
+        for (int k = 0; k < ns; ++k) {
+            const int s = adj ? ns - 1 - k : k;
+            for (int q = 0; q < 2; ++q) {
+                const int colour = adj ? 1 - q : q;
+                const HostTable &t = L.htab[s][colour];
+                for (int b = 0; b < h->grid.batch; ++b) {
+                    double *ub = u + (long long)b * L.d.nn;
+                    const double *fb = f + (long long)b * L.d.nn;
+                    for (const WGDesc &w : t.wgs) {
+                        std::fill(red.begin(), red.end(), 0.0);
+                        for (int ln = 0; ln < w.nchunk; ++ln)
+                            if (L.d.dim == 2)
+                                sweep_phase1<double, 2>(L.d, c, ub, fb, t.chunks[w.chunk0 + ln], ln, r, st[ln]);
+                            else
+                                sweep_phase1<double, 3>(L.d, c, ub, fb, t.chunks[w.chunk0 + ln], ln, r, st[ln]);
+                        for (int bk = 0; bk < w.nblock; ++bk) reduced_solve<double>(t.blocks[w.block0 + bk], r);
+                        for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(ub, ln, r, st[ln]);
+                    }
+                }
+            }
+        }
+    return MG_OK;
+}
+
+} // extern "C"
+

@@ -1,0 +1,116 @@
+// Internal data layout shared by the host driver (twmg.cpp) and the device
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace twmg {
+
+// Lanes per block-relaxation workgroup and maximum points per chunk.  A block
+// (one tweed spider, wireframe ring or zebra line) must fit in one workgroup:
+// at most NT chunks of at most CH points each.
+constexpr int NT = 512;
+constexpr int CH = 16;
+
+// Direction codes: d = 2*axis + (positive ? 1 : 0); the reverse is d ^ 1.
+__host__ __device__ inline int dir_axis(int d) { return d >> 1; }
+__host__ __device__ inline int dir_sign(int d) { return (d & 1) ? 1 : -1; }
+
+enum ChunkFlags : uint8_t {
+    CF_PREV = 1,        // the first point's predecessor (reverse axis direction) is a node of this block
+    CF_NEXT = 2,        // the last point has an in-block successor in direction nextdir
+    CF_NEXT_DIRECT = 4, // ... and that successor is itself a reduced node (not a chunk interior point)
+    CF_JUNCTION = 8,    // the last point is the branch point of a spider (extra in-block directions jmask)
+};
+
+// A chunk: up to CH consecutive collinear points of one leg/line/side.  Its
+// last point is a node of the block's reduced system; the others are
+// eliminated inside the lane that owns the chunk.
+struct Chunk {
+    int16_t c0[3];   // coordinates of the first point
+    uint8_t len;     // 1..CH
+    uint8_t axdir;   // direction of travel along the chunk
+    uint8_t nextdir; // direction from the last point to its successor (CF_NEXT)
+    uint8_t flags;   // ChunkFlags
+    uint8_t jmask;   // CF_JUNCTION: bit d set if direction d from the last point is in-block
+    uint8_t pad0;
+    int16_t prev;    // workgroup-local index of the predecessor node (CF_PREV)
+    int16_t pad1;
+};
+static_assert(sizeof(Chunk) == 16, "chunk descriptor is 16 bytes");
+
+enum BlockType : uint8_t { BT_CHAIN = 0, BT_SPIDER = 1, BT_RING = 2 };
+
+// A block's reduced system: nodes first .. first+count-1 (workgroup-local).
+//  chain : nodes in order, node k couples to k-1 and k+1.
+//  spider: legs 1..m-1 occupy consecutive node ranges ending at ends[l]; leg 0
+//          follows and ends with the branch point (the last node).
+//  ring  : nodes in cyclic order.
+struct Block {
+    int16_t first;
+    int16_t count;
+    uint8_t type;
+    uint8_t m;
+    int16_t ends[7];
+};
+static_assert(sizeof(Block) == 20, "block descriptor is 20 bytes");
+
+struct WGDesc {
+    int chunk0;   // first chunk of this workgroup in the colour's chunk array
+    int nchunk;   // <= NT
+    int block0;   // first block in the colour's block array
+    int nblock;   // <= NT
+};
+
+struct Dims {
+    int dim;
+    int n[3];          // cells per axis (0 beyond dim)
+    long long st[3];   // node strides: 1, nx+1, (nx+1)(ny+1)
+    long long nn;      // nodes per problem
+};
+
+template <typename T> struct Coef {
+    const T *lo[3];    // coefficient toward the -1 neighbour, indexed by the node coordinate
+    const T *hi[3];    // toward the +1 neighbour
+    const T *dg[3];    // contribution of the axis to the diagonal
+};
+
+struct SweepTable {
+    Chunk *chunks = nullptr;
+    Block *blocks = nullptr;
+    WGDesc *wgs = nullptr;
+    int nwg = 0, nchunk = 0, nblock = 0;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+template <typename T>
+hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int batch,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_residual(const Dims &d, const Coef<T> &c, const T *u, const T *f, T *r, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
+                                    T *uc, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f, const T *ainv, int nunk, int batch,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *f, double *partial, int npart,
+                          double *out, int batch, hipStream_t s);
+hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const double *u, const double *f, float *r32,
+                                 double *partial, int npart, double *out, int batch, hipStream_t s);
+hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch, hipStream_t s);
+hipError_t launch_set_boundary(const Dims &d, double *u, const double *bc, int zero_interior, int batch,
+                               hipStream_t s);
+template <typename T> hipError_t launch_fill(T *p, long long n, T v, hipStream_t s);
+hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *lam, const double *w, double *g,
+                          int batch, hipStream_t s);
+
+constexpr int NORM_PARTS = 1024;  // partial-maximum slots used by launch_resnorm
+
+} // namespace twmg
