@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     ap.add_argument("--sweep-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); use --gpus 1",
@@ -66,6 +68,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # a plain copy of known size: FETCH_SIZE and WRITE_SIZE of its kernel
+        # should each read 512 MiB; their ratio to that is the counter scale
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8}))
+        return
 
     import paper_2110_08389_amd as pkg
     from paper_2110_08389_amd import inputs

@@ -765,6 +765,7 @@ static int band_factor(const orc_mg *M, orc_level *L)
 /* u_I = A_II^{-1} (f_I - A_IB u_B): boundary values of u are used as given. */
 static void band_solve(const orc_mg *M, const orc_level *L, double *u, const double *f)
 {
+    if (!L->band && band_factor(M, (orc_level *)L)) { fprintf(stderr, "oracle: banded LU failed\n"); abort(); }
     int dim = M->dim;
     long n = L->nunk;
     int bw = L->bw, w = 2 * bw + 1;
@@ -870,7 +871,7 @@ void *orc_create(int dim, const int *n, double *const *coords, int smoother, int
         if (build_blocks(M, L, 0, k0)) { free(M); return NULL; }
         if (k1 >= 0 && build_blocks(M, L, 1, k1)) { free(M); return NULL; }
     }
-    if (band_factor(M, &M->lev[M->nlev - 1])) { free(M); return NULL; }
+    /* the coarsest level's banded LU is built on first use (band_solve) */
     return M;
 }
 

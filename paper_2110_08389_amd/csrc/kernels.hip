@@ -41,39 +41,223 @@ __device__ __forceinline__ int nrows(const Dims &d, int DIM)
 
 // ---------------------------------------------------------------------------
 // Block relaxation half-sweep: one workgroup per group of whole blocks of one
-// colour; the per-lane steps are in sweep_core.h.
+// colour.  Phase 1 and phase 3 (chunk elimination and back substitution) are
+// per-lane steps in sweep_core.h.  The reduced systems of all blocks of the
+// workgroup are solved together with two workgroup-wide affine scans:
+//   forward   delta_q = alpha_q delta_{q-1} + rhs_q inv_q   (alpha = 0 at segment heads)
+//   backward  x_q     = delta_q - gam_q x_{q+1}             (x_{q+1} -> branch value at tails)
+// with the setup-time factors, so the depth is logarithmic in the block size.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
+
+// inclusive scan of affine maps x -> A x + B in lane order (composition of the
+// maps of lanes 0..t); sa/sb: per-wave totals in LDS
+template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa, T *sb)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T Ap = __shfl_up(A, o, 64), Bp = __shfl_up(B, o, 64);
+        if (lane >= o) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    if (lane == 63) {
+        sa[wv] = A;
+        sb[wv] = B;
+    }
+    __syncthreads();
+    T pA = 1, pB = 0;
+    for (int k = 0; k < wv; ++k) {
+        pB = sa[k] * pB + sb[k];
+        pA = sa[k] * pA;
+    }
+    B = A * pB + B;
+    A = A * pA;
+    __syncthreads();
+}
+
+// the same over lanes in decreasing order (composition of the maps of lanes t..NT-1)
+template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa, T *sb)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T An = __shfl_down(A, o, 64), Bn = __shfl_down(B, o, 64);
+        if (lane + o < 64) {
+            B = A * Bn + B;
+            A = A * An;
+        }
+    }
+    if (lane == 0) {
+        sa[wv] = A;
+        sb[wv] = B;
+    }
+    __syncthreads();
+    T pA = 1, pB = 0;
+    for (int k = nw - 1; k > wv; --k) {
+        pB = sa[k] * pB + sb[k];
+        pA = sa[k] * pA;
+    }
+    B = A * pB + B;
+    A = A * pA;
+    __syncthreads();
+}
+
+// Block-relaxation half-sweep: one lane per chunk.  The workgroup's points are
+// gathered point-major (consecutive lanes read consecutive points of a chunk,
+// so rows are read in whole cache lines) into an LDS staging buffer; each lane
+// then eliminates its chunk's interior (Thomas with zero end values and a left
+// spike), the chunk end points form the blocks' reduced systems, solved by
+// workgroup-wide affine scans with setup-time factors, and each lane
+// back-substitutes its chunk in LDS before the point-major scatter.
+template <typename T, int DIM, int NT>
 __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
-                                                    const WGDesc *__restrict__ wgs)
+                                                    const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
+                                                    int rings)
 {
-    __shared__ T s_low[NT], s_ds[NT], s_rs[NT], s_dn[NT], s_up[NT], s_rn[NT], s_x[NT], s_aux[NT];
-    const RedArrays<T> red{s_low, s_ds, s_rs, s_dn, s_up, s_rn, s_x, s_aux};
+    constexpr int PS = CH + 1; // padded row of the point staging buffer (bank-conflict free)
+    __shared__ T s_pt[NT * PS + 1];
+    __shared__ Chunk s_ch[NT];
+    __shared__ T s_rs[NT], s_rn[NT], s_dl[NT], s_x[NT];
+    __shared__ T s_a[NT / 64], s_b[NT / 64];
+    const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
     const WGDesc w = wgs[blockIdx.x];
     const long long boff = (long long)blockIdx.y * d.nn;
     T *__restrict__ ub = u + boff;
     const T *__restrict__ fb = f + boff;
     const int t = threadIdx.x;
     const bool act = t < w.nchunk;
+    if (act) s_ch[t] = chunks[w.chunk0 + t];
+    __syncthreads();
+    // gather: point-major over the workgroup's chunks, so that consecutive
+    // lanes read consecutive points of a chunk (whole cache lines along rows)
+    {
+        // each batch's loads are issued before any of its results is stored;
+        // slots past the workgroup's points read chunk 0's first point and land
+        // in the spare entry
+        constexpr int GB = (DIM == 2) ? 8 : 4;
+#pragma unroll
+        for (int m0 = 0; m0 < CH; m0 += GB) {
+            T rv[GB];
+            int dst[GB];
+#pragma unroll
+            for (int m = 0; m < GB; ++m) {
+                const int P = t + (m0 + m) * NT, c = P / CH, k = P % CH;
+                const Chunk ch = s_ch[c < w.nchunk ? c : 0];
+                const bool valid = c < w.nchunk && k < ch.len;
+                rv[m] = point_rhs<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
+                dst[m] = valid ? c * PS + k : NT * PS;
+            }
+#pragma unroll
+            for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
+        }
+    }
+    __syncthreads();
     LaneState<T> st;
-    if (act) sweep_phase1<T, DIM>(d, cf, ub, fb, chunks[w.chunk0 + t], t, red, st);
+    uint8_t nfl = 0;
+    int ext = -1;
+    NodeFac<T> nf{0, 0, 0, 0};
+    if (act) {
+        const Chunk ch = s_ch[t];
+        nfl = ch.nflags;
+        ext = ch.ext;
+        nf = fac[w.chunk0 + t];
+        sweep_phase1<T, DIM, false, true>(d, cf, &s_pt[t * PS], ch, t, red, st);
+    }
     __syncthreads();
-    if (t < w.nblock) reduced_solve<T>(blocks[w.block0 + t], red);
+    // forward elimination along segments
+    T rhs = 0, A = 0, B = 0;
+    if (act) {
+        rhs = s_rs[t] + s_rn[t];
+        A = (nfl & NF_HEAD) ? T(0) : nf.alpha;
+        B = rhs * nf.inv;
+    }
+    scan_fwd<T>(A, B, s_a, s_b);
+    const T dl = B;
+    s_dl[t] = dl;
     __syncthreads();
-    if (act) sweep_phase3<T>(ub, t, red, st);
+    // branch points of the spiders
+    if (t < w.nblock) {
+        const Block bk = blocks[w.block0 + t];
+        if (bk.type == BT_SPIDER) {
+            const int J = bk.first + bk.count - 1;
+            const NodeFac<T> fj = fac[w.chunk0 + J];
+            T num = s_rs[J] + s_rn[J];
+            for (int l = 1; l < bk.m; ++l) num -= fac[w.chunk0 + bk.ends[l]].z * s_dl[bk.ends[l]];
+            if (J > bk.first) num -= fj.gam * s_dl[J - 1];
+            s_x[J] = num * fj.inv;
+        }
+    }
+    __syncthreads();
+    // back substitution along segments
+    A = 0;
+    B = 0;
+    if (act) {
+        if (nfl & NF_TAIL) {
+            const T next = (nfl & NF_EXTJ) ? s_x[ext] : T(0);
+            B = dl - nf.gam * next;
+        } else {
+            A = -nf.gam;
+            B = dl;
+        }
+    }
+    scan_bwd<T>(A, B, s_a, s_b);
+    T x = B;
+    if (act && !(nfl & (NF_J | NF_B))) s_x[t] = x;
+    if (rings) {
+        __syncthreads();
+        if (t < w.nblock) {
+            const Block bk = blocks[w.block0 + t];
+            if (bk.type == BT_RING) {
+                const int s0 = bk.first, Bn = bk.first + bk.count - 1;
+                const NodeFac<T> fb_ = fac[w.chunk0 + Bn];
+                s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
+            }
+        }
+        __syncthreads();
+        if (act && (nfl & NF_RING)) x -= s_x[ext] * nf.z;
+        __syncthreads();
+        if (act && (nfl & NF_RING)) s_x[t] = x;
+    }
+    __syncthreads();
+    if (act) sweep_phase3<T>(&s_pt[t * PS], t, red, st);
+    __syncthreads();
+    // scatter, point-major like the gather
+#pragma unroll 4
+    for (int m = 0; m < CH; ++m) {
+        const int P = t + m * NT, c = P / CH, k = P % CH;
+        if (c < w.nchunk && k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
+    }
+}
+
+template <typename T, int DIM>
+static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
+                             const NodeFac<T> *fac, int batch, hipStream_t s)
+{
+    const int rings = tab.rings ? 1 : 0;
+    // workgroups holding a block of more than NT/2 chunks come first and run
+    // with NT lanes; the rest run with NT/2 lanes (a third of the LDS), so that
+    // several workgroups share a CU and hide each other's memory waits
+    if (tab.nwg_big > 0)
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
+                           tab.chunks, tab.blocks, tab.wgs, fac, rings);
+    if (tab.nwg > tab.nwg_big)
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2), 0, s,
+                           d, c, u, f, tab.chunks, tab.blocks, tab.wgs + tab.nwg_big, fac, rings);
 }
 
 template <typename T>
-hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int batch,
-                              hipStream_t s)
+hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
+                              int batch, hipStream_t s)
 {
     if (tab.nwg == 0) return hipSuccess;
-    dim3 grid(tab.nwg, batch);
-    if (d.dim == 2)
-        hipLaunchKernelGGL((k_block_sweep<T, 2>), grid, dim3(NT), 0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs);
-    else
-        hipLaunchKernelGGL((k_block_sweep<T, 3>), grid, dim3(NT), 0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs);
+    const NodeFac<T> *fac;
+    if constexpr (sizeof(T) == 8) fac = tab.fac64[adj];
+    else fac = tab.fac32[adj];
+    if (d.dim == 2) launch_sweep_dim<T, 2>(d, c, u, f, tab, fac, batch, s);
+    else launch_sweep_dim<T, 3>(d, c, u, f, tab, fac, batch, s);
     return hipGetLastError();
 }
 
@@ -497,7 +681,7 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
 // explicit instantiations
 #define TWMG_INST(T)                                                                                                  \
     template hipError_t launch_block_sweep<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, int, \
-                                              hipStream_t);                                                           \
+                                              int, hipStream_t);                                                      \
     template hipError_t launch_checker<T>(const Dims &, const Coef<T> &, T *, const T *, int, int, hipStream_t);     \
     template hipError_t launch_residual<T>(const Dims &, const Coef<T> &, const T *, const T *, T *, int,           \
                                            hipStream_t);                                                              \

@@ -49,6 +49,28 @@ template <typename T, int DIM> __host__ __device__ __forceinline__ T diag_at(con
     return s;
 }
 
+// 1/x: on the device the hardware reciprocal refined by Newton steps (within
+// an ulp of the quotient, and far shorter than a correctly rounded division
+// in the sequential chunk elimination); on the host a plain division.
+template <typename T> __host__ __device__ __forceinline__ T rcp(T x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = __builtin_fma(-x, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-x, r, 1.0);
+        return __builtin_fma(r, e, r);
+    } else {
+        float r = __builtin_amdgcn_rcpf(x);
+        const float e = __builtin_fmaf(-x, r, 1.0f);
+        return __builtin_fmaf(r, e, r);
+    }
+#else
+    return T(1) / x;
+#endif
+}
+
 // the reduced-system arrays of one workgroup (LDS on the device)
 template <typename T> struct RedArrays {
     T *low;  // coupling of node q's row to its predecessor node
@@ -69,19 +91,69 @@ template <typename T> struct LaneState {
     const T *Pfwd;
 };
 
-// Phase 1: right-hand sides, chunk-interior elimination, reduced equations.
+// Right-hand side of point k of a chunk: f minus the couplings to every
+// neighbour outside the block (other colour, or boundary nodes).
 template <typename T, int DIM>
-__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
-                                                      const T *__restrict__ fb, const Chunk &ch, int t,
-                                                      const RedArrays<T> &s, LaneState<T> &st)
+__host__ __device__ __forceinline__ T point_rhs(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                                const T *__restrict__ fb, const Chunk &ch, int k)
+{
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const bool hp = ch.flags & CF_PREV, hn = ch.flags & CF_NEXT, jn = ch.flags & CF_JUNCTION;
+    const int ci = ch.c0[0] + (ax == 0 ? sg * k : 0), cj = ch.c0[1] + (ax == 1 ? sg * k : 0),
+              cl = (DIM == 3) ? ch.c0[2] + (ax == 2 ? sg * k : 0) : 0;
+    const long long idx = ci + cj * d.st[1] + (DIM == 3 ? cl * d.st[2] : 0);
+    unsigned inb = 0;
+    if (k > 0 || hp) inb |= 1u << (ad ^ 1);
+    if (k < L - 1) inb |= 1u << ad;
+    else {
+        if (hn) inb |= 1u << ch.nextdir;
+        if (jn) inb |= ch.jmask;
+    }
+    // every neighbour of an interior point exists, so all loads are issued
+    // unconditionally (no branches: the compiler can start them all at once)
+    // and in-block terms are dropped by a select
+    T r = fb[idx];
+#pragma unroll
+    for (int dd = 0; dd < 2 * DIM; ++dd) {
+        const int cc = (dd >> 1) == 0 ? ci : ((dd >> 1) == 1 ? cj : cl);
+        const T term = coef_arr<T>(cf, dd)[cc] * ub[idx + dir_off(d, dd)];
+        r -= ((inb >> dd) & 1u) ? T(0) : term;
+    }
+    return r;
+}
+
+// node stride along axis a (selects: no indexed access to the argument struct)
+__host__ __device__ __forceinline__ long long axis_stride(const Dims &d, int a)
+{
+    return (a == 0) ? 1LL : ((a == 1) ? d.st[1] : d.st[2]);
+}
+
+// node index of point k of a chunk
+__host__ __device__ __forceinline__ long long point_index(const Dims &d, const Chunk &ch, int k)
+{
+    const int ax = ch.axdir >> 1, sg = (ch.axdir & 1) ? 1 : -1;
+    return (long long)ch.c0[0] + (long long)ch.c0[1] * d.st[1] + (long long)ch.c0[2] * d.st[2] +
+           (long long)(sg * k) * axis_stride(d, ax);
+}
+
+// Phase 1: right-hand sides, chunk-interior elimination, reduced equations.
+// DATA: build the right-hand-side part (reads u, f); MATRIX: build the
+// geometry-only reduced matrix (low, ds, dn, up, aux), used at setup to factor
+// the reduced systems once.  The kernel runs DATA only.
+// rr[k] holds the right-hand side of point k (point_rhs), staged by the caller.
+template <typename T, int DIM, bool MATRIX, bool DATA>
+__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, const T *__restrict__ rr,
+                                                      const Chunk &ch, int t, const RedArrays<T> &s,
+                                                      LaneState<T> &st)
 {
     const int L = ch.len;
     const int ad = ch.axdir, ax = ad >> 1;
     const int sg = (ad & 1) ? 1 : -1;
     const uint8_t fl = ch.flags;
-    const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT, jn = fl & CF_JUNCTION;
+    const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
-    const long long step = sg * d.st[ax];
+    const long long step = sg * axis_stride(d, ax);
     const long long p0 = c0x + c0y * d.st[1] + (DIM == 3 ? c0z * d.st[2] : 0);
     const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
     const T *Pback = coef_arr_rt<T, DIM>(cf, ad ^ 1);
@@ -96,229 +168,157 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     st.cax = cax;
     st.Pfwd = Pfwd;
 
-    T Gp = 0, Dp = 0, Sp = hp ? T(1) : T(0);
-    T rL = 0, aL = 0, bL = 0, cL = 0;
+    // coefficients along the chunk, all loaded before the elimination chain so
+    // that their latency is paid once: a (toward the predecessor point), c
+    // (toward the successor) and the diagonal b = along-axis part + fixed part
+    const T *Pdg = (ax == 0) ? cf.dg[0] : ((ax == 1) ? cf.dg[1] : cf.dg[DIM == 3 ? 2 : 1]);
+    T bfix = 0;
+    if (ax != 0) bfix += cf.dg[0][c0x];
+    if (ax != 1) bfix += cf.dg[1][c0y];
+    if (DIM == 3 && ax != 2) bfix += cf.dg[2][c0z];
+    T Av[CH], Cv[CH], Bv[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-        if (k < L) {
-            const int ci = c0x + k * ex, cj = c0y + k * ey, cl = c0z + k * ez;
-            const long long idx = p0 + k * step;
-            unsigned inb = 0;
-            if (k > 0 || hp) inb |= 1u << (ad ^ 1);
-            if (k < L - 1) inb |= 1u << ad;
-            else {
-                if (hn) inb |= 1u << ch.nextdir;
-                if (jn) inb |= ch.jmask;
-            }
-            T r = fb[idx];
-#pragma unroll
-            for (int dd = 0; dd < 2 * DIM; ++dd) {
-                if (!((inb >> dd) & 1u)) {
-                    const int cc = (dd >> 1) == 0 ? ci : ((dd >> 1) == 1 ? cj : cl);
-                    r -= coef_arr<T>(cf, dd)[cc] * ub[idx + dir_off(d, dd)];
-                }
-            }
-            const T b = diag_at<T, DIM>(cf, ci, cj, cl);
-            const int ca = cax + k * sg;
-            const T a = Pback[ca];
-            if (k < L - 1) {
-                const T cc = Pfwd[ca];
-                const T inv = T(1) / (b - a * Gp);
-                st.G[k] = cc * inv;
-                st.D[k] = (r - a * Dp) * inv;
-                st.S[k] = -a * Sp * inv;
-                Gp = st.G[k];
-                Dp = st.D[k];
-                Sp = st.S[k];
-            } else {
-                rL = r;
-                aL = a;
-                bL = b;
-                if (hn) {
-                    const int nx = ch.nextdir, na = nx >> 1, ns = (nx & 1) ? 1 : -1;
-                    const int cn = (na == 0) ? ci : ((na == 1) ? cj : cl);
-                    cL = coef_arr_rt<T, DIM>(cf, nx)[cn];
-                    if (nd) {
-                        // the successor's row coefficient back toward this point
-                        s.aux[t] = coef_arr_rt<T, DIM>(cf, nx ^ 1)[cn + ns];
-                    }
-                }
-            }
+        const int ca = (k < L) ? cax + k * sg : cax; // clamped: stays inside the arrays
+        Av[k] = Pback[ca];
+        Cv[k] = Pfwd[ca];
+        Bv[k] = Pdg[ca];
+    }
+    // the last point's row (the node): a, b, its right-hand side, and its
+    // coupling to the successor
+    const int cL_ = cax + (L - 1) * sg;
+    const T aL = Pback[cL_];
+    const T bL = (ax == 0) ? Pdg[cL_] + bfix : bfix + Pdg[cL_];
+    const T rL = DATA ? rr[L - 1] : T(0);
+    T cL = 0;
+    if (hn) {
+        const int li = c0x + (L - 1) * ex, lj = c0y + (L - 1) * ey, ll = c0z + (L - 1) * ez;
+        const int nx = ch.nextdir, na = nx >> 1, ns = (nx & 1) ? 1 : -1;
+        const int cn = (na == 0) ? li : ((na == 1) ? lj : ll);
+        cL = coef_arr_rt<T, DIM>(cf, nx)[cn];
+        if (MATRIX && nd) {
+            // the successor's row coefficient back toward this point
+            s.aux[t] = coef_arr_rt<T, DIM>(cf, nx ^ 1)[cn + ns];
         }
+    }
+    // elimination of the interior (points 0..L-2) with zero end values; run
+    // branch-free over all CH positions, entries from L-1 on are not used
+    T Gp = 0, Dp = 0, Sp = hp ? T(1) : T(0);
+#pragma unroll
+    for (int k = 0; k < CH - 1; ++k) {
+        const T r = DATA ? rr[k] : T(0);
+        const T b = (ax == 0) ? Bv[k] + bfix : bfix + Bv[k];
+        const T a = Av[k];
+        const T inv = rcp<T>(b - a * Gp);
+        st.G[k] = Cv[k] * inv;
+        st.D[k] = (r - a * Dp) * inv;
+        st.S[k] = -a * Sp * inv;
+        Gp = st.G[k];
+        Dp = st.D[k];
+        Sp = st.S[k];
     }
     // first-point values of the zero-end interior solution y and its spikes v, w
     T yl = 0, vl = 0, wl = 0, y = 0, v = 0, ww = 0;
 #pragma unroll
     for (int k = CH - 2; k >= 0; --k) {
-        if (k == L - 2) {
-            y = st.D[k];
-            v = st.S[k];
-            ww = -st.G[k];
-            yl = y;
-            vl = v;
-            wl = ww;
-        } else if (k < L - 2) {
-            y = st.D[k] - st.G[k] * y;
-            v = st.S[k] - st.G[k] * v;
-            ww = -st.G[k] * ww;
+        const bool last = (k == L - 2), in = (k < L - 2);
+        y = last ? st.D[k] : (in ? st.D[k] - st.G[k] * y : y);
+        yl = last ? y : yl;
+        if (MATRIX) {
+            v = last ? st.S[k] : (in ? st.S[k] - st.G[k] * v : v);
+            ww = last ? -st.G[k] : (in ? -st.G[k] * ww : ww);
+            vl = last ? v : vl;
+            wl = last ? ww : wl;
         }
     }
-    if (L >= 2) {
-        s.ds[t] = bL + aL * wl;
-        s.low[t] = hp ? aL * vl : T(0);
-        s.rs[t] = rL - aL * yl;
-    } else {
-        s.ds[t] = bL;
-        s.low[t] = hp ? aL : T(0);
-        s.rs[t] = rL;
+    // own row: a_L x_{L-2} + b_L X + c_L x_next = r_L with x_{L-2} = y + v X_prev + w X
+    if (DATA) s.rs[t] = (L >= 2) ? rL - aL * yl : rL;
+    if (MATRIX) {
+        s.ds[t] = (L >= 2) ? bL + aL * wl : bL;
+        s.low[t] = hp ? ((L >= 2) ? aL * vl : aL) : T(0);
     }
-    if (!hn) {
-        s.dn[t] = 0;
-        s.up[t] = 0;
-        s.rn[t] = 0;
-    } else if (nd) {
-        s.dn[t] = 0;
-        s.up[t] = cL;
-        s.rn[t] = 0;
+    // the successor's first interior point couples the successor node's row to
+    // this interior; without one, the coupling is direct (or absent)
+    if (!hn || nd) {
+        if (DATA) s.rn[t] = 0;
+        if (MATRIX) {
+            s.dn[t] = 0;
+            s.up[t] = hn ? cL : T(0);
+        }
     }
     if (hp && L >= 2) {
         const T cprev = Pfwd[cax - sg];
-        s.dn[ch.prev] = cprev * v;
-        s.up[ch.prev] = cprev * ww;
-        s.rn[ch.prev] = -cprev * y;
+        if (DATA) s.rn[ch.prev] = -cprev * y;
+        if (MATRIX) {
+            s.dn[ch.prev] = cprev * v;
+            s.up[ch.prev] = cprev * ww;
+        }
     }
 }
 
-// Phase 2: one lane solves one block's reduced system.
-template <typename T> __host__ __device__ void reduced_solve(const Block &bk, const RedArrays<T> &r)
-{
-    const int s = bk.first, e = s + bk.count;
-    for (int q = s; q < e; ++q) {
-        r.ds[q] += r.dn[q];
-        r.rs[q] += r.rn[q];
-    }
-    if (bk.type == BT_CHAIN) {
-        T g = 0, dl = 0;
-        for (int q = s; q < e; ++q) {
-            const T lo = r.low[q];
-            const T inv = T(1) / (r.ds[q] - lo * g);
-            g = r.up[q] * inv;
-            dl = (r.rs[q] - lo * dl) * inv;
-            r.up[q] = g;
-            r.rs[q] = dl;
-        }
-        T x = r.rs[e - 1];
-        r.x[e - 1] = x;
-        for (int q = e - 2; q >= s; --q) {
-            x = r.rs[q] - r.up[q] * x;
-            r.x[q] = x;
-        }
-    } else if (bk.type == BT_SPIDER) {
-        // m-legged Thomas: eliminate every leg from its tip toward the branch
-        // point, solve the branch row, substitute back out to the tips.
-        const int J = e - 1;
-        T num = r.rs[J], den = r.ds[J];
-        int start = s;
-        for (int l = 1; l < bk.m; ++l) {
-            const int end = bk.ends[l];
-            T g = 0, dl = 0;
-            for (int q = start; q <= end; ++q) {
-                const T lo = r.low[q];
-                const T inv = T(1) / (r.ds[q] - lo * g);
-                g = r.up[q] * inv;
-                dl = (r.rs[q] - lo * dl) * inv;
-                r.up[q] = g;
-                r.rs[q] = dl;
-            }
-            const T dJ = r.aux[end];
-            num -= dJ * dl;
-            den -= dJ * g;
-            start = end + 1;
-        }
-        {
-            T g = 0, dl = 0;
-            for (int q = start; q < J; ++q) {
-                const T lo = r.low[q];
-                const T inv = T(1) / (r.ds[q] - lo * g);
-                g = r.up[q] * inv;
-                dl = (r.rs[q] - lo * dl) * inv;
-                r.up[q] = g;
-                r.rs[q] = dl;
-            }
-            if (J > start) {
-                const T lo = r.low[J];
-                num -= lo * dl;
-                den -= lo * g;
-            }
-        }
-        const T xJ = num / den;
-        r.x[J] = xJ;
-        start = s;
-        for (int l = 1; l < bk.m; ++l) {
-            const int end = bk.ends[l];
-            T x = xJ;
-            for (int q = end; q >= start; --q) {
-                x = r.rs[q] - r.up[q] * x;
-                r.x[q] = x;
-            }
-            start = end + 1;
-        }
-        T x = xJ;
-        for (int q = J - 1; q >= start; --q) {
-            x = r.rs[q] - r.up[q] * x;
-            r.x[q] = x;
-        }
-    } else {
-        // ring: border on the last node; the open tridiagonal rows s..B-1 are
-        // solved for the right-hand side (y) and for the border's column (z),
-        // then the border row closes the system.
-        const int B = e - 1;
-        const T colS = r.low[s], colE = r.up[B - 1];
-        T g = 0, dy = 0, dz = 0;
-        for (int q = s; q < B; ++q) {
-            const T lo = (q > s) ? r.low[q] : T(0);
-            const T up = (q < B - 1) ? r.up[q] : T(0);
-            const T col = (q == s ? colS : T(0)) + (q == B - 1 ? colE : T(0));
-            const T inv = T(1) / (r.ds[q] - lo * g);
-            g = up * inv;
-            dy = (r.rs[q] - lo * dy) * inv;
-            dz = (col - lo * dz) * inv;
-            r.up[q] = g;
-            r.rs[q] = dy;
-            r.dn[q] = dz;
-        }
-        T y = r.rs[B - 1], z = r.dn[B - 1];
-        r.x[B - 1] = y;
-        r.rn[B - 1] = z;
-        for (int q = B - 2; q >= s; --q) {
-            y = r.rs[q] - r.up[q] * y;
-            z = r.dn[q] - r.up[q] * z;
-            r.x[q] = y;
-            r.rn[q] = z;
-        }
-        const T lowB = r.low[B], upB = r.up[B];
-        const T xB = (r.rs[B] - lowB * r.x[B - 1] - upB * r.x[s]) / (r.ds[B] - lowB * r.rn[B - 1] - upB * r.rn[s]);
-        r.x[B] = xB;
-        for (int q = s; q < B; ++q) r.x[q] = r.x[q] - xB * r.rn[q];
-    }
-}
-
-// Phase 3: back-substitution of the chunk interior from the node values.
+// Phase 2 on the host: the reduced systems of one workgroup solved node by
+// node with the setup-time factors, in the order the device scans use.
+// rhs[q] = rs[q] + rn[q]; on return x[q] holds every node value.
 template <typename T>
-__host__ __device__ __forceinline__ void sweep_phase3(T *__restrict__ ub, int t, const RedArrays<T> &s,
+__host__ void reduced_solve_seq(int n, const Chunk *ch, const NodeFac<T> *fac, const T *rhs, T *dl, T *x)
+{
+    // forward elimination along segments
+    T carry = 0;
+    for (int q = 0; q < n; ++q) {
+        const bool head = ch[q].nflags & NF_HEAD;
+        dl[q] = (head ? T(0) : fac[q].alpha * carry) + rhs[q] * fac[q].inv;
+        carry = dl[q];
+    }
+    // branch points
+    for (int q = 0; q < n; ++q)
+        if (ch[q].nflags & NF_J) {
+            // branch row: legs 1..m-1 end next to the branch point (coupling z
+            // of their last node); leg 0's last node precedes it (coupling gam)
+            const int p0 = (ch[q].flags & CF_PREV) ? ch[q].prev : -1;
+            T num = rhs[q];
+            for (int p = 0; p < n; ++p)
+                if ((ch[p].nflags & NF_EXTJ) && ch[p].ext == q && p != p0) num -= fac[p].z * dl[p];
+            if (p0 >= 0) num -= fac[q].gam * dl[p0];
+            x[q] = num * fac[q].inv;
+        }
+    // back substitution along segments
+    T next = 0;
+    for (int q = n - 1; q >= 0; --q) {
+        const uint8_t f = ch[q].nflags;
+        if (f & (NF_J | NF_B)) continue;
+        if (f & NF_TAIL) next = (f & NF_EXTJ) ? x[ch[q].ext] : T(0);
+        x[q] = dl[q] - fac[q].gam * next;
+        next = x[q];
+    }
+    // ring borders, then the ring corrections
+    for (int q = 0; q < n; ++q)
+        if (ch[q].nflags & NF_B) {
+            int s = q;
+            while (s > 0 && (ch[s - 1].nflags & NF_RING) && ch[s - 1].ext == q) --s;
+            x[q] = (rhs[q] - fac[q].alpha * x[q - 1] - fac[q].gam * x[s]) * fac[q].inv;
+        }
+    for (int q = 0; q < n; ++q)
+        if (ch[q].nflags & NF_RING) x[q] -= x[ch[q].ext] * fac[q].z;
+}
+
+// Phase 3: back-substitution of the chunk interior from the node values;
+// xx[k] receives the new value of point k (the caller scatters it to u).
+template <typename T>
+__host__ __device__ __forceinline__ void sweep_phase3(T *__restrict__ xx, int t, const RedArrays<T> &s,
                                                       const LaneState<T> &st)
 {
     const T Xp = st.hp ? s.x[st.prev] : T(0);
     const T Xo = s.x[t];
     T x = Xo;
+    // branch-free: positions past the interior keep x = Xo; entries k >= L of
+    // xx are scratch and never scattered
 #pragma unroll
     for (int k = CH - 2; k >= 0; --k) {
-        if (k <= st.L - 2) {
-            x = st.D[k] + st.S[k] * Xp - st.G[k] * x;
-            ub[st.p0 + k * st.step] = x;
-        }
+        const T xn = st.D[k] + st.S[k] * Xp - st.G[k] * x;
+        x = (k <= st.L - 2) ? xn : x;
+        xx[k] = x;
     }
-    ub[st.p0 + (st.L - 1) * st.step] = Xo;
+    xx[st.L - 1] = Xo;
 }
 
 } // namespace twmg

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -401,6 +402,44 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
         } else {
             return MG_EUNSUPPORTED;
         }
+        // node roles in the reduced-system scans (block-local indices)
+        {
+            const int nc = (int)hb.ch.size();
+            for (Chunk &c : hb.ch) {
+                c.nflags = 0;
+                c.ext = -1;
+            }
+            auto seg = [&](int a, int z) {
+                hb.ch[a].nflags |= NF_HEAD;
+                hb.ch[z].nflags |= NF_TAIL;
+            };
+            if (hb.type == BT_CHAIN) {
+                seg(0, nc - 1);
+            } else if (hb.type == BT_SPIDER) {
+                const int J = nc - 1;
+                int start = 0;
+                for (int lg = 1; lg < hb.m; ++lg) {
+                    seg(start, hb.ends[lg]);
+                    hb.ch[hb.ends[lg]].nflags |= NF_EXTJ;
+                    hb.ch[hb.ends[lg]].ext = (int16_t)J;
+                    start = hb.ends[lg] + 1;
+                }
+                if (start < J) {
+                    seg(start, J - 1);
+                    hb.ch[J - 1].nflags |= NF_EXTJ;
+                    hb.ch[J - 1].ext = (int16_t)J;
+                }
+                hb.ch[J].nflags |= NF_HEAD | NF_TAIL | NF_J;
+            } else {
+                const int B = nc - 1;
+                seg(0, B - 1);
+                for (int q = 0; q < B; ++q) {
+                    hb.ch[q].nflags |= NF_RING;
+                    hb.ch[q].ext = (int16_t)B;
+                }
+                hb.ch[B].nflags |= NF_HEAD | NF_TAIL | NF_B;
+            }
+        }
         // successor links: direct when the successor chunk has no interior
         for (size_t k = 0; k < hb.ch.size(); ++k) {
             const int sc = hb.succ[k];
@@ -417,39 +456,65 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
 struct HostTable {
     std::vector<Chunk> chunks;
     std::vector<Block> blocks;
-    std::vector<WGDesc> wgs;
+    std::vector<WGDesc> wgs;  // the first nbig need NT lanes, the rest NT/2
+    int nbig = 0;
 };
 
 void pack(std::vector<const HostBlock *> bl, HostTable &t)
 {
     std::stable_sort(bl.begin(), bl.end(),
                      [](const HostBlock *a, const HostBlock *b) { return a->ch.size() > b->ch.size(); });
-    WGDesc cur{0, 0, 0, 0};
-    auto flush = [&]() {
-        if (cur.nchunk) t.wgs.push_back(cur);
-        cur = WGDesc{(int)t.chunks.size(), 0, (int)t.blocks.size(), 0};
-    };
-    flush();
-    for (const HostBlock *hb : bl) {
-        const int nc = (int)hb->ch.size();
-        if (cur.nchunk + nc > NT || cur.nblock + 1 > NT) flush();
-        const int o = cur.nchunk;
-        for (Chunk c : hb->ch) {
-            if (c.flags & CF_PREV) c.prev = (int16_t)(c.prev + o);
-            t.chunks.push_back(c);
+    // blocks of more than NT/2 chunks get a full NT-lane workgroup each; the
+    // rest are packed into NT/2-lane workgroups
+    for (int pass = 0; pass < 2; ++pass) {
+        const int cap = pass == 0 ? NT : NT / 2;
+        const size_t w0 = t.wgs.size();
+        WGDesc cur{0, 0, 0, 0};
+        auto flush = [&]() {
+            if (cur.nchunk) t.wgs.push_back(cur);
+            cur = WGDesc{(int)t.chunks.size(), 0, (int)t.blocks.size(), 0};
+        };
+        flush();
+        for (const HostBlock *hb : bl) {
+            const int nc = (int)hb->ch.size();
+            if ((pass == 0) != (nc > NT / 2)) continue;
+            if (cur.nchunk + nc > cap || cur.nblock + 1 > cap) flush();
+            const int o = cur.nchunk;
+            for (Chunk c : hb->ch) {
+                if (c.flags & CF_PREV) c.prev = (int16_t)(c.prev + o);
+                if (c.ext >= 0) c.ext = (int16_t)(c.ext + o);
+                t.chunks.push_back(c);
+            }
+            Block bk;
+            std::memset(&bk, 0, sizeof(bk));
+            bk.first = (int16_t)o;
+            bk.count = (int16_t)nc;
+            bk.type = (uint8_t)hb->type;
+            bk.m = (uint8_t)hb->m;
+            for (int k = 0; k < 7; ++k) bk.ends[k] = (int16_t)(hb->ends[k] + o);
+            t.blocks.push_back(bk);
+            cur.nchunk += nc;
+            cur.nblock += 1;
         }
-        Block bk;
-        std::memset(&bk, 0, sizeof(bk));
-        bk.first = (int16_t)o;
-        bk.count = (int16_t)nc;
-        bk.type = (uint8_t)hb->type;
-        bk.m = (uint8_t)hb->m;
-        for (int k = 0; k < 7; ++k) bk.ends[k] = (int16_t)(hb->ends[k] + o);
-        t.blocks.push_back(bk);
-        cur.nchunk += nc;
-        cur.nblock += 1;
+        flush();
+        if (pass == 0) t.nbig = (int)t.wgs.size();
+        // Workgroups are handed to the 8 XCDs round-robin in index order.
+        // Number them so that consecutive entries of the list (blocks of
+        // neighbouring labels, which read the same cache lines) share an XCD
+        // and its L2: within each group of 256, entry w goes to XCD w/ceil(size/8).
+        if (!std::getenv("TWMG_NO_XCD_ORDER")) {
+            const int n = (int)(t.wgs.size() - w0), G = 256;
+            std::vector<WGDesc> out(n);
+            for (int g0 = 0; g0 < n; g0 += G) {
+                const int s = std::min(G, n - g0), q = (s + 7) / 8;
+                std::vector<std::pair<int, int>> key(s);
+                for (int w = 0; w < s; ++w) key[w] = {(w % q) * 8 + w / q, w};
+                std::sort(key.begin(), key.end());
+                for (int r = 0; r < s; ++r) out[g0 + r] = t.wgs[w0 + g0 + key[r].second];
+            }
+            std::copy(out.begin(), out.end(), t.wgs.begin() + w0);
+        }
     }
-    flush();
 }
 
 // Bounds check of a table against its grid before it is uploaded: every
@@ -458,13 +523,17 @@ void pack(std::vector<const HostBlock *> bl, HostTable &t)
 bool validate(const Grid3 &g, const HostTable &t)
 {
     const int nc = (int)t.chunks.size(), nb = (int)t.blocks.size();
-    for (const WGDesc &w : t.wgs) {
-        if (w.chunk0 < 0 || w.nchunk < 1 || w.nchunk > NT || w.chunk0 + w.nchunk > nc) return false;
-        if (w.block0 < 0 || w.nblock < 1 || w.nblock > NT || w.block0 + w.nblock > nb) return false;
+    for (size_t wi = 0; wi < t.wgs.size(); ++wi) {
+        const WGDesc &w = t.wgs[wi];
+        const int cap = ((int)wi < t.nbig) ? NT : NT / 2;
+        if (w.chunk0 < 0 || w.nchunk < 1 || w.nchunk > cap || w.chunk0 + w.nchunk > nc) return false;
+        if (w.block0 < 0 || w.nblock < 1 || w.nblock > cap || w.block0 + w.nblock > nb) return false;
         for (int k = 0; k < w.nchunk; ++k) {
             const Chunk &c = t.chunks[w.chunk0 + k];
             if (c.len < 1 || c.len > CH || c.axdir >= 2 * g.dim || c.nextdir >= 2 * g.dim) return false;
             if ((c.flags & CF_PREV) && (c.prev < 0 || c.prev >= w.nchunk)) return false;
+            if (c.ext < -1 || c.ext >= w.nchunk) return false;
+            if ((c.nflags & (NF_EXTJ | NF_RING)) && c.ext < 0) return false;
             const int ax = c.axdir >> 1, sg = (c.axdir & 1) ? 1 : -1;
             int p[3] = {c.c0[0], c.c0[1], g.dim == 3 ? c.c0[2] : 0};
             p[ax] -= sg;
@@ -501,6 +570,79 @@ bool validate(const Grid3 &g, const HostTable &t)
     return true;
 }
 
+// Factor the reduced systems of one table (geometry only).  Phase 1 of the
+// sweep is run on the host without data to obtain each node's reduced row,
+// then every segment is eliminated once; the kernel only substitutes.
+template <int DIM>
+void factor_table(const Dims &d, const Coef<double> &c, const HostTable &t, std::vector<NodeFac<double>> &fac)
+{
+    fac.assign(t.chunks.size(), NodeFac<double>{0, 0, 0, 0});
+    std::vector<double> low(NT), ds(NT), rs(NT), dn(NT), up(NT), rn(NT), xx(NT), aux(NT);
+    RedArrays<double> r{low.data(), ds.data(), rs.data(), dn.data(), up.data(), rn.data(), xx.data(), aux.data()};
+    LaneState<double> st;
+    for (const WGDesc &w : t.wgs) {
+        std::fill(low.begin(), low.end(), 0.0);
+        std::fill(ds.begin(), ds.end(), 0.0);
+        std::fill(dn.begin(), dn.end(), 0.0);
+        std::fill(up.begin(), up.end(), 0.0);
+        std::fill(aux.begin(), aux.end(), 0.0);
+        const Chunk *ch = &t.chunks[w.chunk0];
+        NodeFac<double> *F = &fac[w.chunk0];
+        for (int q = 0; q < w.nchunk; ++q) sweep_phase1<double, DIM, true, false>(d, c, nullptr, ch[q], q, r, st);
+        std::vector<double> dg(w.nchunk);
+        for (int q = 0; q < w.nchunk; ++q) dg[q] = ds[q] + dn[q];
+        auto segment = [&](int a, int z, bool open_tail) {
+            double g = 0;
+            for (int q = a; q <= z; ++q) {
+                const double lo = (q == a) ? 0.0 : low[q];
+                const double u = (q == z && open_tail) ? 0.0 : up[q];
+                const double inv = 1.0 / (dg[q] - lo * g);
+                F[q].alpha = -lo * inv;
+                F[q].inv = inv;
+                F[q].gam = u * inv;
+                g = F[q].gam;
+            }
+        };
+        for (int k = 0; k < w.nblock; ++k) {
+            const Block &bk = t.blocks[w.block0 + k];
+            const int s = bk.first, e = s + bk.count;
+            if (bk.type == BT_CHAIN) {
+                segment(s, e - 1, false);
+            } else if (bk.type == BT_SPIDER) {
+                const int J = e - 1;
+                int start = s;
+                double den = dg[J];
+                for (int l = 1; l < bk.m; ++l) {
+                    const int end = bk.ends[l];
+                    segment(start, end, false);
+                    F[end].z = aux[end];
+                    den -= aux[end] * F[end].gam;
+                    start = end + 1;
+                }
+                const bool leg0 = ch[J].flags & CF_PREV;
+                if (leg0) {
+                    segment(start, J - 1, false);
+                    den -= low[J] * F[J - 1].gam;
+                }
+                F[J] = NodeFac<double>{0.0, 1.0 / den, leg0 ? low[J] : 0.0, 0.0};
+            } else {
+                const int B = e - 1;
+                segment(s, B - 1, true);
+                // border column of the open part: low at its head, up at its tail
+                std::vector<double> dz(B - s), z(B - s);
+                for (int q = s; q < B; ++q) {
+                    const double col = (q == s ? low[s] : 0.0) + (q == B - 1 ? up[B - 1] : 0.0);
+                    dz[q - s] = (q == s ? 0.0 : F[q].alpha * dz[q - s - 1]) + col * F[q].inv;
+                }
+                for (int q = B - 1; q >= s; --q) z[q - s] = dz[q - s] - (q == B - 1 ? 0.0 : F[q].gam * z[q - s + 1]);
+                for (int q = s; q < B; ++q) F[q].z = z[q - s];
+                const double inv = 1.0 / (dg[B] - low[B] * z[B - 1 - s] - up[B] * z[0]);
+                F[B] = NodeFac<double>{low[B], inv, up[B], 0.0};
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------
@@ -533,6 +675,7 @@ struct Level {
     Coef<float> c32[2];
     SweepTable tab[2][2]; // [motif slot][colour]
     HostTable htab[2][2]; // host copies (validation and the host emulation hook)
+    std::vector<NodeFac<double>> hfac[2][2][2]; // [slot][colour][forward/transposed]
     std::vector<double> hco[2][3][3]; // [fwd/transposed][lo,hi,dg][axis]
     Coef<double> hc64[2];
     double *u = nullptr, *f = nullptr;   // FP64 work arrays (levels >= 1)
@@ -814,8 +957,22 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 T.blocks = h->pool.upload(t.blocks, err);
                 T.wgs = h->pool.upload(t.wgs, err);
                 T.nwg = (int)t.wgs.size();
+                T.nwg_big = t.nbig;
                 T.nchunk = (int)t.chunks.size();
                 T.nblock = (int)t.blocks.size();
+                for (const Block &bk : t.blocks)
+                    if (bk.type == BT_RING) T.rings = true;
+                for (int adj = 0; adj < 2; ++adj) {
+                    std::vector<NodeFac<double>> &f64 = L.hfac[s][colour][adj];
+                    if (dim == 2) factor_table<2>(L.d, L.hc64[adj], t, f64);
+                    else factor_table<3>(L.d, L.hc64[adj], t, f64);
+                    std::vector<NodeFac<float>> f32(f64.size());
+                    for (size_t q = 0; q < f64.size(); ++q)
+                        f32[q] = NodeFac<float>{(float)f64[q].alpha, (float)f64[q].inv, (float)f64[q].gam,
+                                                (float)f64[q].z};
+                    T.fac64[adj] = h->pool.upload(f64, err);
+                    T.fac32[adj] = h->pool.upload(f32, err);
+                }
                 if (err) return err;
             }
         }
@@ -897,7 +1054,7 @@ template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
         const int s = adj ? ns - 1 - k : k;
         for (int q = 0; q < 2; ++q) {
             const int colour = adj ? 1 - q : q;
-            HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], B, h->stream));
+            HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], adj, B, h->stream));
         }
     }
     return MG_OK;
@@ -1248,6 +1405,7 @@ int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int n
     RedArrays<double> r{&red[0], &red[NT], &red[2 * NT], &red[3 * NT], &red[4 * NT], &red[5 * NT], &red[6 * NT],
                         &red[7 * NT]};
     std::vector<LaneState<double>> st(NT);
+    std::vector<double> rhs(NT), dl(NT), pt((size_t)NT * CH);
     const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
     for (int it = 0; it < nu; ++it)
         for (int k = 0; k < ns; ++k) {
@@ -1258,15 +1416,26 @@ int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int n
                 for (int b = 0; b < h->grid.batch; ++b) {
                     double *ub = u + (long long)b * L.d.nn;
                     const double *fb = f + (long long)b * L.d.nn;
+                    const std::vector<NodeFac<double>> &fac = L.hfac[s][colour][adj];
                     for (const WGDesc &w : t.wgs) {
                         std::fill(red.begin(), red.end(), 0.0);
+                        const Chunk *chs = &t.chunks[w.chunk0];
                         for (int ln = 0; ln < w.nchunk; ++ln)
+                            for (int k = 0; k < chs[ln].len; ++k)
+                                pt[ln * CH + k] = (L.d.dim == 2) ? point_rhs<double, 2>(L.d, c, ub, fb, chs[ln], k)
+                                                                 : point_rhs<double, 3>(L.d, c, ub, fb, chs[ln], k);
+                        for (int ln = 0; ln < w.nchunk; ++ln) {
                             if (L.d.dim == 2)
-                                sweep_phase1<double, 2>(L.d, c, ub, fb, t.chunks[w.chunk0 + ln], ln, r, st[ln]);
+                                sweep_phase1<double, 2, false, true>(L.d, c, &pt[ln * CH], chs[ln], ln, r, st[ln]);
                             else
-                                sweep_phase1<double, 3>(L.d, c, ub, fb, t.chunks[w.chunk0 + ln], ln, r, st[ln]);
-                        for (int bk = 0; bk < w.nblock; ++bk) reduced_solve<double>(t.blocks[w.block0 + bk], r);
-                        for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(ub, ln, r, st[ln]);
+                                sweep_phase1<double, 3, false, true>(L.d, c, &pt[ln * CH], chs[ln], ln, r, st[ln]);
+                        }
+                        for (int ln = 0; ln < w.nchunk; ++ln) rhs[ln] = r.rs[ln] + r.rn[ln];
+                        reduced_solve_seq<double>(w.nchunk, &t.chunks[w.chunk0], &fac[w.chunk0], rhs.data(),
+                                                  dl.data(), r.x);
+                        for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(&pt[ln * CH], ln, r, st[ln]);
+                        for (int ln = 0; ln < w.nchunk; ++ln)
+                            for (int k = 0; k < chs[ln].len; ++k) ub[point_index(L.d, chs[ln], k)] = pt[ln * CH + k];
                     }
                 }
             }

@@ -34,9 +34,30 @@ struct Chunk {
     uint8_t nextdir; // direction from the last point to its successor (CF_NEXT)
     uint8_t flags;   // ChunkFlags
     uint8_t jmask;   // CF_JUNCTION: bit d set if direction d from the last point is in-block
-    uint8_t pad0;
+    uint8_t nflags;  // NodeFlags of the chunk's node in its block's reduced system
     int16_t prev;    // workgroup-local index of the predecessor node (CF_PREV)
-    int16_t pad1;
+    int16_t ext;     // workgroup-local index of the branch point (leg ends) or ring border node
+};
+
+// Role of a node in the reduced-system solve.  Nodes are solved by two affine
+// scans over the workgroup: forward elimination along each segment (a leg, a
+// chain, or a ring opened at its border node), then back substitution.
+enum NodeFlags : uint8_t {
+    NF_HEAD = 1,  // first node of a segment
+    NF_TAIL = 2,  // last node of a segment
+    NF_J = 4,     // branch point of a spider (solved from the leg ends)
+    NF_B = 8,     // border node of a ring (solved last)
+    NF_RING = 16, // node of a ring's open part (corrected by the border value)
+    NF_EXTJ = 32, // segment tail coupled to the branch point ext
+};
+
+// Setup-time factorisation of a node's reduced row (geometry only).
+//  ordinary node: alpha = -lower*inv (0 at a head), inv = 1/pivot, gam = upper*inv,
+//                 z = ring: border-column solution; leg end: branch row's coupling to it
+//  branch point : inv = 1/(branch pivot), gam = its coupling to the node before it
+//  ring border  : alpha = its lower coupling, inv = 1/(closing pivot), gam = its upper coupling
+template <typename T> struct NodeFac {
+    T alpha, inv, gam, z;
 };
 static_assert(sizeof(Chunk) == 16, "chunk descriptor is 16 bytes");
 
@@ -80,13 +101,17 @@ struct SweepTable {
     Chunk *chunks = nullptr;
     Block *blocks = nullptr;
     WGDesc *wgs = nullptr;
+    NodeFac<double> *fac64[2] = {nullptr, nullptr}; // [forward, transposed operator]
+    NodeFac<float> *fac32[2] = {nullptr, nullptr};
     int nwg = 0, nchunk = 0, nblock = 0;
+    int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others at most NT/2
+    bool rings = false;
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
 template <typename T>
-hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int batch,
-                              hipStream_t s);
+hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
+                              int batch, hipStream_t s);
 template <typename T>
 hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s);
 template <typename T>
