@@ -111,11 +111,84 @@ template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa
 // spike), the chunk end points form the blocks' reduced systems, solved by
 // workgroup-wide affine scans with setup-time factors, and each lane
 // back-substitutes its chunk in LDS before the point-major scatter.
+// Phase 2: the reduced systems of the workgroup's blocks (lane = node), from
+// the node rows s_rs + s_rn left by phase 1; the node values land in s_x.
+template <typename T>
+__device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint8_t nfl, int ext, const NodeFac<T> &nf,
+                                                 const Block *__restrict__ blocks, const NodeFac<T> *__restrict__ fac,
+                                                 int rings, T *s_rs, T *s_rn, T *s_dl, T *s_x, T *s_a, T *s_b)
+{
+    const int t = threadIdx.x;
+    // forward elimination along segments
+    T rhs = 0, A = 0, B = 0;
+    if (act) {
+        rhs = s_rs[t] + s_rn[t];
+        A = (nfl & NF_HEAD) ? T(0) : nf.alpha;
+        B = rhs * nf.inv;
+    }
+    scan_fwd<T>(A, B, s_a, s_b);
+    const T dl = B;
+    s_dl[t] = dl;
+    __syncthreads();
+    // branch points of the spiders
+    if (t < w.nblock) {
+        // leg ends are read through the pointer: a private copy of the block
+        // indexed by the loop counter would live in scratch memory
+        const Block *bp = &blocks[w.block0 + t];
+        const int type = bp->type, first = bp->first, count = bp->count, m = bp->m;
+        if (type == BT_SPIDER) {
+            const int J = first + count - 1;
+            const NodeFac<T> fj = fac[w.chunk0 + J];
+            T num = s_rs[J] + s_rn[J];
+            for (int l = 1; l < m; ++l) {
+                const int e = bp->ends[l];
+                num -= fac[w.chunk0 + e].z * s_dl[e];
+            }
+            if (J > first) num -= fj.gam * s_dl[J - 1];
+            s_x[J] = num * fj.inv;
+        }
+    }
+    __syncthreads();
+    // back substitution along segments
+    A = 0;
+    B = 0;
+    if (act) {
+        if (nfl & NF_TAIL) {
+            const T next = (nfl & NF_EXTJ) ? s_x[ext] : T(0);
+            B = dl - nf.gam * next;
+        } else {
+            A = -nf.gam;
+            B = dl;
+        }
+    }
+    scan_bwd<T>(A, B, s_a, s_b);
+    T x = B;
+    if (act && !(nfl & (NF_J | NF_B))) s_x[t] = x;
+    if (rings) {
+        __syncthreads();
+        if (t < w.nblock) {
+            const Block bk = blocks[w.block0 + t];
+            if (bk.type == BT_RING) {
+                const int s0 = bk.first, Bn = bk.first + bk.count - 1;
+                const NodeFac<T> fb_ = fac[w.chunk0 + Bn];
+                s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
+            }
+        }
+        __syncthreads();
+        if (act && (nfl & NF_RING)) x -= s_x[ext] * nf.z;
+        __syncthreads();
+        if (act && (nfl & NF_RING)) s_x[t] = x;
+    }
+}
+
+// The work of one workgroup descriptor w; ub / fb may point to global memory
+// or to LDS (the coarse-level kernel keeps its levels there).  All NT lanes of
+// the workgroup must call it.
 template <typename T, int DIM, int NT>
-__global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
-                                                    const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
-                                                    const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
-                                                    int rings)
+__device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
+                                         const T *__restrict__ fb, const Chunk *__restrict__ chunks,
+                                         const Block *__restrict__ blocks, const WGDesc w,
+                                         const NodeFac<T> *__restrict__ fac, int rings)
 {
     constexpr int PS = CH + 1; // padded row of the point staging buffer (bank-conflict free)
     __shared__ T s_pt[NT * PS + 1];
@@ -123,10 +196,6 @@ __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__res
     __shared__ T s_rs[NT], s_rn[NT], s_dl[NT], s_x[NT];
     __shared__ T s_a[NT / 64], s_b[NT / 64];
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
-    const WGDesc w = wgs[blockIdx.x];
-    const long long boff = (long long)blockIdx.y * d.nn;
-    T *__restrict__ ub = u + boff;
-    const T *__restrict__ fb = f + boff;
     const int t = threadIdx.x;
     const bool act = t < w.nchunk;
     if (act) s_ch[t] = chunks[w.chunk0 + t];
@@ -164,63 +233,11 @@ __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__res
         nfl = ch.nflags;
         ext = ch.ext;
         nf = fac[w.chunk0 + t];
-        sweep_phase1<T, DIM, false, true>(d, cf, &s_pt[t * PS], ch, t, red, st);
+        const T *rp = &s_pt[t * PS];
+        sweep_phase1<T, DIM, false, true>(d, cf, [&](int k) { return rp[k]; }, rp[ch.len - 1], ch, t, red, st);
     }
     __syncthreads();
-    // forward elimination along segments
-    T rhs = 0, A = 0, B = 0;
-    if (act) {
-        rhs = s_rs[t] + s_rn[t];
-        A = (nfl & NF_HEAD) ? T(0) : nf.alpha;
-        B = rhs * nf.inv;
-    }
-    scan_fwd<T>(A, B, s_a, s_b);
-    const T dl = B;
-    s_dl[t] = dl;
-    __syncthreads();
-    // branch points of the spiders
-    if (t < w.nblock) {
-        const Block bk = blocks[w.block0 + t];
-        if (bk.type == BT_SPIDER) {
-            const int J = bk.first + bk.count - 1;
-            const NodeFac<T> fj = fac[w.chunk0 + J];
-            T num = s_rs[J] + s_rn[J];
-            for (int l = 1; l < bk.m; ++l) num -= fac[w.chunk0 + bk.ends[l]].z * s_dl[bk.ends[l]];
-            if (J > bk.first) num -= fj.gam * s_dl[J - 1];
-            s_x[J] = num * fj.inv;
-        }
-    }
-    __syncthreads();
-    // back substitution along segments
-    A = 0;
-    B = 0;
-    if (act) {
-        if (nfl & NF_TAIL) {
-            const T next = (nfl & NF_EXTJ) ? s_x[ext] : T(0);
-            B = dl - nf.gam * next;
-        } else {
-            A = -nf.gam;
-            B = dl;
-        }
-    }
-    scan_bwd<T>(A, B, s_a, s_b);
-    T x = B;
-    if (act && !(nfl & (NF_J | NF_B))) s_x[t] = x;
-    if (rings) {
-        __syncthreads();
-        if (t < w.nblock) {
-            const Block bk = blocks[w.block0 + t];
-            if (bk.type == BT_RING) {
-                const int s0 = bk.first, Bn = bk.first + bk.count - 1;
-                const NodeFac<T> fb_ = fac[w.chunk0 + Bn];
-                s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
-            }
-        }
-        __syncthreads();
-        if (act && (nfl & NF_RING)) x -= s_x[ext] * nf.z;
-        __syncthreads();
-        if (act && (nfl & NF_RING)) s_x[t] = x;
-    }
+    reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
     __syncthreads();
     if (act) sweep_phase3<T>(&s_pt[t * PS], t, red, st);
     __syncthreads();
@@ -230,6 +247,16 @@ __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__res
         const int P = t + m * NT, c = P / CH, k = P % CH;
         if (c < w.nchunk && k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
     }
+}
+
+template <typename T, int DIM, int NT>
+__global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+                                                    const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
+                                                    const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
+                                                    int rings)
+{
+    const long long boff = (long long)blockIdx.y * d.nn;
+    sweep_wg<T, DIM, NT>(d, cf, u + boff, f + boff, chunks, blocks, wgs[blockIdx.x], fac, rings);
 }
 
 template <typename T, int DIM>
@@ -265,6 +292,18 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
 // Checkerboard (red-black point Gauss-Seidel) half-sweep: Section 2, Fig. 1.
 // red = (i + j [+ l]) even.
 // ---------------------------------------------------------------------------
+
+// point Gauss-Seidel value at interior node (i, j, l) with index p
+template <typename T, int DIM>
+__device__ __forceinline__ T point_gs(const Dims &d, const Coef<T> &cf, const T *ub, const T *fb, int i, int j, int l,
+                                      long long p)
+{
+    T s = fb[p] - cf.lo[0][i] * ub[p - 1] - cf.hi[0][i] * ub[p + 1] - cf.lo[1][j] * ub[p - d.st[1]] -
+          cf.hi[1][j] * ub[p + d.st[1]];
+    if (DIM == 3) s -= cf.lo[2][l] * ub[p - d.st[2]] + cf.hi[2][l] * ub[p + d.st[2]];
+    return s / diag_at<T, DIM>(cf, i, j, l);
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_checker(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                  int colour)
@@ -279,10 +318,7 @@ __global__ void __launch_bounds__(256) k_checker(Dims d, Coef<T> cf, T *__restri
         const int i0 = 1 + ((1 + j + l + colour) & 1);
         for (int i = i0 + 2 * threadIdx.x; i < d.n[0]; i += 2 * blockDim.x) {
             const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
-            T s = fb[p] - cf.lo[0][i] * ub[p - 1] - cf.hi[0][i] * ub[p + 1] - cf.lo[1][j] * ub[p - d.st[1]] -
-                  cf.hi[1][j] * ub[p + d.st[1]];
-            if (DIM == 3) s -= cf.lo[2][l] * ub[p - d.st[2]] + cf.hi[2][l] * ub[p + d.st[2]];
-            ub[p] = s / diag_at<T, DIM>(cf, i, j, l);
+            ub[p] = point_gs<T, DIM>(d, cf, ub, fb, i, j, l, p);
         }
     }
 }
@@ -331,6 +367,31 @@ hipError_t launch_residual(const Dims &d, const Coef<T> &c, const T *u, const T 
 // around fine node 2I; also clears the coarse correction u_c there (step 4).
 // ---------------------------------------------------------------------------
 template <typename T, int DIM>
+__device__ __forceinline__ T restrict_at(const Dims &fd, const Coef<T> &cf, const T *ub, const T *fb, int I, int J,
+                                         int K)
+{
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = 0;
+#pragma unroll
+    for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            T rowacc = 0;
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                const int i = 2 * I + a, j = 2 * J + b, l = (DIM == 3) ? 2 * K + c : 0;
+                if (interior<DIM>(fd, i, j, l)) {
+                    const long long p = i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0);
+                    rowacc += w3[a + 1] * defect_at<T, DIM>(fd, cf, ub, fb, i, j, l, p);
+                }
+            }
+            acc += (DIM == 3 ? w3[c + 1] : T(1)) * w3[b + 1] * rowacc;
+        }
+    }
+    return acc;
+}
+
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coef<T> cf, const T *__restrict__ u,
                                                            const T *__restrict__ f, T *__restrict__ fc,
                                                            T *__restrict__ uc)
@@ -339,30 +400,12 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coe
     const T *fb = f + (long long)blockIdx.y * fd.nn;
     const long long cboff = (long long)blockIdx.y * cd.nn;
     const int rows = nrows(cd, DIM);
-    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
         const int J = row % (cd.n[1] + 1), K = row / (cd.n[1] + 1);
         if (J == 0 || J == cd.n[1] || (DIM == 3 && (K == 0 || K == cd.n[2]))) continue;
         for (int I = 1 + threadIdx.x; I < cd.n[0]; I += blockDim.x) {
-            T acc = 0;
-#pragma unroll
-            for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
-#pragma unroll
-                for (int b = -1; b <= 1; ++b) {
-                    T rowacc = 0;
-#pragma unroll
-                    for (int a = -1; a <= 1; ++a) {
-                        const int i = 2 * I + a, j = 2 * J + b, l = (DIM == 3) ? 2 * K + c : 0;
-                        if (interior<DIM>(fd, i, j, l)) {
-                            const long long p = i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0);
-                            rowacc += w3[a + 1] * defect_at<T, DIM>(fd, cf, ub, fb, i, j, l, p);
-                        }
-                    }
-                    acc += (DIM == 3 ? w3[c + 1] : T(1)) * w3[b + 1] * rowacc;
-                }
-            }
             const long long q = cboff + I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0);
-            fc[q] = acc;
+            fc[q] = restrict_at<T, DIM>(fd, cf, ub, fb, I, J, K);
             uc[q] = T(0);
         }
     }
@@ -382,6 +425,26 @@ hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T
 // Fused bilinear/trilinear prolongation + update (Section 4, fused step 5):
 // u += P e_c in index space; e_c's boundary entries are zero.
 // ---------------------------------------------------------------------------
+// interpolated coarse correction at fine interior node (i, j, l): weights 1
+// (even index) or 1/2 + 1/2 (odd index) per axis
+template <typename T, int DIM>
+__device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int j, int l)
+{
+    const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
+    const int K0 = l >> 1, K1 = (l + 1) >> 1;
+    auto cval = [&](int I, int J, int K) -> T { return eb[I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0)]; };
+    T pl[2];
+#pragma unroll
+    for (int kk = 0; kk < (DIM == 3 ? 2 : 1); ++kk) {
+        const int K = kk ? K1 : K0;
+        const T r0 = (I0 == I1) ? cval(I0, J0, K) : T(0.5) * (cval(I0, J0, K) + cval(I1, J0, K));
+        const T r1 = (I0 == I1) ? cval(I0, J1, K) : T(0.5) * (cval(I0, J1, K) + cval(I1, J1, K));
+        pl[kk] = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
+    }
+    if (DIM == 2) return pl[0];
+    return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
 {
@@ -391,32 +454,8 @@ __global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
         const int j = row % (fd.n[1] + 1), l = row / (fd.n[1] + 1);
         if (j == 0 || j == fd.n[1] || (DIM == 3 && (l == 0 || l == fd.n[2]))) continue;
-        const int J0 = j >> 1, J1 = (j + 1) >> 1;
-        const int K0 = l >> 1, K1 = (l + 1) >> 1;
-        for (int i = 1 + threadIdx.x; i < fd.n[0]; i += blockDim.x) {
-            const int I0 = i >> 1, I1 = (i + 1) >> 1;
-            // weights 1 (even index) or 1/2 + 1/2 (odd index) per axis
-            auto cval = [&](int I, int J, int K) -> T {
-                return eb[I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0)];
-            };
-            T v;
-            if (DIM == 2) {
-                const T r0 = (I0 == I1) ? cval(I0, J0, 0) : T(0.5) * (cval(I0, J0, 0) + cval(I1, J0, 0));
-                const T r1 = (I0 == I1) ? cval(I0, J1, 0) : T(0.5) * (cval(I0, J1, 0) + cval(I1, J1, 0));
-                v = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
-            } else {
-                T pl[2];
-#pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    const int K = kk ? K1 : K0;
-                    const T r0 = (I0 == I1) ? cval(I0, J0, K) : T(0.5) * (cval(I0, J0, K) + cval(I1, J0, K));
-                    const T r1 = (I0 == I1) ? cval(I0, J1, K) : T(0.5) * (cval(I0, J1, K) + cval(I1, J1, K));
-                    pl[kk] = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
-                }
-                v = (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
-            }
-            ub[i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0)] += v;
-        }
+        for (int i = 1 + threadIdx.x; i < fd.n[0]; i += blockDim.x)
+            ub[i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0)] += prolong_at<T, DIM>(cd, eb, i, j, l);
     }
 }
 
@@ -433,13 +472,11 @@ hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u,
 // Coarsest-level direct solve (Section 4 step 4): u_I = A_II^{-1}(f_I - A_IB u_B)
 // with the inverse precomputed at setup; one workgroup per batch problem.
 // ---------------------------------------------------------------------------
+// the whole workgroup; rhs: nunk entries of workgroup scratch (LDS)
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_coarse_solve(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
-                                                      const T *__restrict__ ainv, int nunk)
+__device__ __forceinline__ void coarse_solve_wg(const Dims &d, const Coef<T> &cf, T *ub, const T *fb,
+                                                const T *__restrict__ ainv, int nunk, T *rhs)
 {
-    __shared__ T rhs[1024];
-    T *ub = u + (long long)blockIdx.x * d.nn;
-    const T *fb = f + (long long)blockIdx.x * d.nn;
     const int nx = d.n[0] - 1, ny = d.n[1] - 1;
     for (int q = threadIdx.x; q < nunk; q += blockDim.x) {
         const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = (DIM == 3) ? 1 + q / (nx * ny) : 0;
@@ -465,12 +502,157 @@ __global__ void __launch_bounds__(256) k_coarse_solve(Dims d, Coef<T> cf, T *__r
     }
 }
 
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_coarse_solve(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+                                                      const T *__restrict__ ainv, int nunk)
+{
+    __shared__ T rhs[1024];
+    T *ub = u + (long long)blockIdx.x * d.nn;
+    const T *fb = f + (long long)blockIdx.x * d.nn;
+    coarse_solve_wg<T, DIM>(d, cf, ub, fb, ainv, nunk, rhs);
+}
+
 template <typename T>
 hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f, const T *ainv, int nunk, int batch,
                                hipStream_t s)
 {
     if (d.dim == 2) hipLaunchKernelGGL((k_coarse_solve<T, 2>), dim3(batch), dim3(256), 0, s, d, c, u, f, ainv, nunk);
     else hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(batch), dim3(256), 0, s, d, c, u, f, ainv, nunk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level sub-cycle in one workgroup per problem (Section 4 steps 1-6 on
+// the levels that fit in LDS).  Everything the sub-cycle reads lives in LDS:
+// the read-only image (level descriptors, coefficients, block tables and the
+// operation list) is copied in first, then the first tail level's u and f.
+// The operations run with barriers between them, and u is copied back.  With
+// no global memory access inside the cycle, each operation costs LDS latency
+// and barriers only.
+// ---------------------------------------------------------------------------
+
+// Block sweep of one workgroup descriptor with u, f, coefficients and tables
+// in LDS: each lane forms its chunk's right-hand sides directly (no staging),
+// phases 1-3 as in the main sweep, new values written in place.
+template <typename T, int DIM>
+__device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, T *ub, const T *fb,
+                                              const Chunk *chunks, const Block *blocks, const WGDesc w,
+                                              const NodeFac<T> *fac, int rings, T *s_rs, T *s_rn, T *s_dl, T *s_x,
+                                              T *s_a, T *s_b)
+{
+    const int t = threadIdx.x;
+    const bool act = t < w.nchunk;
+    const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
+    LaneState<T> st;
+    uint8_t nfl = 0;
+    int ext = -1;
+    NodeFac<T> nf{0, 0, 0, 0};
+    Chunk ch = chunks[w.chunk0];
+    if (act) {
+        ch = chunks[w.chunk0 + t];
+        nfl = ch.nflags;
+        ext = ch.ext;
+        nf = fac[w.chunk0 + t];
+        const int L = ch.len;
+        const T rL = point_rhs<T, DIM>(d, cf, ub, fb, ch, L - 1);
+        sweep_phase1<T, DIM, false, true>(
+            d, cf, [&](int k) { return point_rhs<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0); }, rL, ch, t, red, st);
+    }
+    __syncthreads();
+    reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
+    __syncthreads();
+    if (act) sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[point_index(d, ch, k)] = v; });
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__restrict__ u, const T *__restrict__ f)
+{
+    __shared__ __align__(16) unsigned char s_mem[TAIL_BYTES];
+    __shared__ T s_rs[TAIL_NT], s_rn[TAIL_NT], s_dl[TAIL_NT], s_x[TAIL_NT];
+    __shared__ T s_a[TAIL_NT / 64], s_b[TAIL_NT / 64];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.image);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_mem);
+        for (int q = threadIdx.x; q < P.image_bytes / 16; q += blockDim.x) dst[q] = src[q];
+    }
+    __syncthreads();
+    const TailLevel *lev = reinterpret_cast<const TailLevel *>(s_mem + P.lev_off);
+    const TailOp *ops = reinterpret_cast<const TailOp *>(s_mem + P.ops_off);
+    auto arr = [&](int off) { return reinterpret_cast<T *>(s_mem + off); };
+    auto coef = [&](const TailLevel &L) { return make_coef<T>(arr(L.co), L.cs); };
+    const long long boff = (long long)blockIdx.x * P.nn0;
+    T *ug = u + boff;
+    const T *fg = f + boff;
+    {
+        T *u0 = arr(lev[0].uoff), *f0 = arr(lev[0].foff);
+        for (int q = threadIdx.x; q < (int)P.nn0; q += blockDim.x) {
+            u0[q] = ug[q];
+            f0[q] = fg[q];
+        }
+    }
+    __syncthreads();
+    for (int o = 0; o < P.nops; ++o) {
+        const TailOp op = ops[o];
+        const TailLevel &L = lev[op.lv];
+        T *us = arr(L.uoff);
+        const T *fs = arr(L.foff);
+        const Dims d = L.d;
+        const Coef<T> cf = coef(L);
+        if (op.kind == TO_SWEEP) {
+            const int sl = op.slot, c = op.colour, nw = L.nwg[sl][c];
+            const Chunk *chunks = reinterpret_cast<const Chunk *>(s_mem + L.chunk_off[sl][c]);
+            const Block *blocks = reinterpret_cast<const Block *>(s_mem + L.block_off[sl][c]);
+            const WGDesc *wgs = reinterpret_cast<const WGDesc *>(s_mem + L.wg_off[sl][c]);
+            const NodeFac<T> *fac = reinterpret_cast<const NodeFac<T> *>(s_mem + L.fac_off[sl][c]);
+            for (int w = 0; w < nw; ++w) {
+                sweep_wg_tail<T, DIM>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c], s_rs, s_rn, s_dl,
+                                      s_x, s_a, s_b);
+                __syncthreads();
+            }
+        } else if (op.kind == TO_CHECKER) {
+            const int nx = d.n[0] - 1, ny = d.n[1] - 1, nz = DIM == 3 ? d.n[2] - 1 : 1;
+            for (int q = threadIdx.x; q < nx * ny * nz; q += blockDim.x) {
+                const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = DIM == 3 ? 1 + q / (nx * ny) : 0;
+                if (((i + j + l) & 1) != op.colour) continue;
+                const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+                us[p] = point_gs<T, DIM>(d, cf, us, fs, i, j, l, p);
+            }
+        } else if (op.kind == TO_RESTRICT) {
+            const TailLevel &C = lev[op.lv + 1];
+            const Dims cd = C.d;
+            T *uc = arr(C.uoff);
+            T *fc = arr(C.foff);
+            for (int q = threadIdx.x; q < (int)cd.nn; q += blockDim.x) {
+                const int I = q % (cd.n[0] + 1), J = (q / (cd.n[0] + 1)) % (cd.n[1] + 1),
+                          K = DIM == 3 ? q / ((cd.n[0] + 1) * (cd.n[1] + 1)) : 0;
+                fc[q] = interior<DIM>(cd, I, J, K) ? restrict_at<T, DIM>(d, cf, us, fs, I, J, K) : T(0);
+                uc[q] = T(0);
+            }
+        } else if (op.kind == TO_PROLONG) {
+            const TailLevel &C = lev[op.lv + 1];
+            const Dims cd = C.d;
+            const T *uc = arr(C.uoff);
+            const int nx = d.n[0] - 1, ny = d.n[1] - 1, nz = DIM == 3 ? d.n[2] - 1 : 1;
+            for (int q = threadIdx.x; q < nx * ny * nz; q += blockDim.x) {
+                const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = DIM == 3 ? 1 + q / (nx * ny) : 0;
+                us[i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0)] += prolong_at<T, DIM>(cd, uc, i, j, l);
+            }
+        } else { // TO_SOLVE
+            coarse_solve_wg<T, DIM>(d, cf, us, fs, P.ainv, P.nunk, arr(P.rhs_off));
+        }
+        __syncthreads();
+    }
+    {
+        const T *u0 = arr(lev[0].uoff);
+        for (int q = threadIdx.x; q < (int)P.nn0; q += blockDim.x) ug[q] = u0[q];
+    }
+}
+
+template <typename T>
+hipError_t launch_tail_cycle(const TailPlan<T> &p, T *u, const T *f, int batch, hipStream_t s)
+{
+    if (p.dim == 2) hipLaunchKernelGGL((k_tail_cycle<T, 2>), dim3(batch), dim3(TAIL_NT), 0, s, p, u, f);
+    else hipLaunchKernelGGL((k_tail_cycle<T, 3>), dim3(batch), dim3(TAIL_NT), 0, s, p, u, f);
     return hipGetLastError();
 }
 
@@ -692,7 +874,8 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
                                                hipStream_t);                                                          \
     template hipError_t launch_resnorm<T>(const Dims &, const Coef<T> &, const T *, const T *, double *, int,        \
                                           double *, int, hipStream_t);                                                \
-    template hipError_t launch_fill<T>(T *, long long, T, hipStream_t);
+    template hipError_t launch_fill<T>(T *, long long, T, hipStream_t);                                             \
+    template hipError_t launch_tail_cycle<T>(const TailPlan<T> &, T *, const T *, int, hipStream_t);
 
 TWMG_INST(double)
 TWMG_INST(float)

@@ -28,18 +28,15 @@ template <typename T> __host__ __device__ __forceinline__ const T *coef_arr(cons
     return (d & 1) ? cf.hi[d >> 1] : cf.lo[d >> 1];
 }
 
-// coefficient array of a per-lane direction d (selects, no indexed loads)
+// coefficient array of a per-lane direction d, and diagonal part of a per-lane
+// axis: offsets into the level's coefficient block
 template <typename T, int DIM> __host__ __device__ __forceinline__ const T *coef_arr_rt(const Coef<T> &cf, int d)
 {
-    const T *p = cf.lo[0];
-    p = (d == 1) ? cf.hi[0] : p;
-    p = (d == 2) ? cf.lo[1] : p;
-    p = (d == 3) ? cf.hi[1] : p;
-    if (DIM == 3) {
-        p = (d == 4) ? cf.lo[2] : p;
-        p = (d == 5) ? cf.hi[2] : p;
-    }
-    return p;
+    return cf.base + d * cf.cs;
+}
+template <typename T> __host__ __device__ __forceinline__ const T *dg_arr_rt(const Coef<T> &cf, int ax)
+{
+    return cf.base + (6 + ax) * cf.cs;
 }
 
 template <typename T, int DIM> __host__ __device__ __forceinline__ T diag_at(const Coef<T> &cf, int i, int j, int l)
@@ -141,9 +138,11 @@ __host__ __device__ __forceinline__ long long point_index(const Dims &d, const C
 // DATA: build the right-hand-side part (reads u, f); MATRIX: build the
 // geometry-only reduced matrix (low, ds, dn, up, aux), used at setup to factor
 // the reduced systems once.  The kernel runs DATA only.
-// rr[k] holds the right-hand side of point k (point_rhs), staged by the caller.
-template <typename T, int DIM, bool MATRIX, bool DATA>
-__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, const T *__restrict__ rr,
+// rr(k) returns the right-hand side of point k (point_rhs) for k < CH - 1; it
+// is called once per k, in increasing order, so it may compute the value on
+// the spot.  rL is the right-hand side of the last point (index len - 1).
+template <typename T, int DIM, bool MATRIX, bool DATA, typename RR>
+__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
                                                       const Chunk &ch, int t, const RedArrays<T> &s,
                                                       LaneState<T> &st)
 {
@@ -171,7 +170,7 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     // coefficients along the chunk, all loaded before the elimination chain so
     // that their latency is paid once: a (toward the predecessor point), c
     // (toward the successor) and the diagonal b = along-axis part + fixed part
-    const T *Pdg = (ax == 0) ? cf.dg[0] : ((ax == 1) ? cf.dg[1] : cf.dg[DIM == 3 ? 2 : 1]);
+    const T *Pdg = dg_arr_rt<T>(cf, ax);
     T bfix = 0;
     if (ax != 0) bfix += cf.dg[0][c0x];
     if (ax != 1) bfix += cf.dg[1][c0y];
@@ -189,7 +188,6 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     const int cL_ = cax + (L - 1) * sg;
     const T aL = Pback[cL_];
     const T bL = (ax == 0) ? Pdg[cL_] + bfix : bfix + Pdg[cL_];
-    const T rL = DATA ? rr[L - 1] : T(0);
     T cL = 0;
     if (hn) {
         const int li = c0x + (L - 1) * ex, lj = c0y + (L - 1) * ey, ll = c0z + (L - 1) * ez;
@@ -206,7 +204,7 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     T Gp = 0, Dp = 0, Sp = hp ? T(1) : T(0);
 #pragma unroll
     for (int k = 0; k < CH - 1; ++k) {
-        const T r = DATA ? rr[k] : T(0);
+        const T r = DATA ? rr(k) : T(0);
         const T b = (ax == 0) ? Bv[k] + bfix : bfix + Bv[k];
         const T a = Av[k];
         const T inv = rcp<T>(b - a * Gp);
@@ -299,6 +297,24 @@ __host__ void reduced_solve_seq(int n, const Chunk *ch, const NodeFac<T> *fac, c
         }
     for (int q = 0; q < n; ++q)
         if (ch[q].nflags & NF_RING) x[q] -= x[ch[q].ext] * fac[q].z;
+}
+
+// Phase 3 with a store callback: put(k, x_k) for k = 0 .. len-1 (used where u
+// is written in place, as in the coarse-level kernel).
+template <typename T, typename F>
+__host__ __device__ __forceinline__ void sweep_phase3_each(int t, const RedArrays<T> &s, const LaneState<T> &st,
+                                                           F &&put)
+{
+    const T Xp = st.hp ? s.x[st.prev] : T(0);
+    const T Xo = s.x[t];
+    T x = Xo;
+#pragma unroll
+    for (int k = CH - 2; k >= 0; --k) {
+        const T xn = st.D[k] + st.S[k] * Xp - st.G[k] * x;
+        x = (k <= st.L - 2) ? xn : x;
+        if (k <= st.L - 2) put(k, x);
+    }
+    put(st.L - 1, Xo);
 }
 
 // Phase 3: back-substitution of the chunk interior from the node values;

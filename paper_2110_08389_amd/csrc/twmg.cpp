@@ -588,7 +588,7 @@ void factor_table(const Dims &d, const Coef<double> &c, const HostTable &t, std:
         std::fill(aux.begin(), aux.end(), 0.0);
         const Chunk *ch = &t.chunks[w.chunk0];
         NodeFac<double> *F = &fac[w.chunk0];
-        for (int q = 0; q < w.nchunk; ++q) sweep_phase1<double, DIM, true, false>(d, c, nullptr, ch[q], q, r, st);
+        for (int q = 0; q < w.nchunk; ++q) sweep_phase1<double, DIM, true, false>(d, c, [](int) { return 0.0; }, 0.0, ch[q], q, r, st);
         std::vector<double> dg(w.nchunk);
         for (int q = 0; q < w.nchunk; ++q) dg[q] = ds[q] + dn[q];
         auto segment = [&](int a, int z, bool open_tail) {
@@ -676,7 +676,8 @@ struct Level {
     SweepTable tab[2][2]; // [motif slot][colour]
     HostTable htab[2][2]; // host copies (validation and the host emulation hook)
     std::vector<NodeFac<double>> hfac[2][2][2]; // [slot][colour][forward/transposed]
-    std::vector<double> hco[2][3][3]; // [fwd/transposed][lo,hi,dg][axis]
+    long long cs = 0;                 // entries per coefficient array
+    std::vector<double> hblk[2];      // host coefficient blocks [forward, transposed] (layout of Coef)
     Coef<double> hc64[2];
     double *u = nullptr, *f = nullptr;   // FP64 work arrays (levels >= 1)
     float *u32 = nullptr, *f32 = nullptr; // FP32 work arrays (all levels)
@@ -701,6 +702,12 @@ struct mg_handle {
     size_t ws_bytes = 0;
     char *ws = nullptr;
     bool ws_owned = false;
+    // coarse-level kernel: levels tail_lv .. nlev-1 run in one workgroup per problem
+    int tail_lv = -1;
+    void *tail_img[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // [FP64, FP32][forward, transposed]
+    TailPlan<double> tail64[2];
+    TailPlan<float> tail32[2];
+    int tail_key[4] = {-1, -1, -1, -1}; // checker, nu1, nu2, gamma the images were built for
 };
 
 namespace {
@@ -834,6 +841,163 @@ int motif_slots(int smoother, int dim, int *m0, int *m1, bool *checker)
     return MG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// coarse-level kernel set-up.  The kernel takes the longest run of coarsest
+// levels (at least two) whose LDS image (level descriptors, coefficients, block
+// tables, operation list) plus u, f and the coarsest solve's scratch fit in
+// TAIL_BYTES, and whose blocks fit its workgroup.  The operation list depends
+// on the cycle options, so the images are rebuilt when those change.
+// TWMG_NO_TAIL=1 keeps every level on the per-level kernels.
+// ---------------------------------------------------------------------------
+void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, std::vector<TailOp> &ops)
+{
+    const uint8_t rel = (uint8_t)(lv - lt);
+    if (lv == h->nlev - 1) {
+        ops.push_back(TailOp{TO_SOLVE, rel, 0, 0});
+        return;
+    }
+    auto relax = [&]() {
+        if (h->checker) {
+            for (int k = 0; k < 2; ++k) ops.push_back(TailOp{TO_CHECKER, rel, 0, (uint8_t)(adj ? 1 - k : k)});
+            return;
+        }
+        const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+        for (int k = 0; k < ns; ++k) {
+            const int sl = adj ? ns - 1 - k : k;
+            for (int q = 0; q < 2; ++q) ops.push_back(TailOp{TO_SWEEP, rel, (uint8_t)sl, (uint8_t)(adj ? 1 - q : q)});
+        }
+    };
+    for (int k = 0; k < h->opt.nu1; ++k) relax();
+    ops.push_back(TailOp{TO_RESTRICT, rel, 0, 0});
+    for (int g = 0; g < h->opt.gamma; ++g) tail_ops_rec(h, lt, lv + 1, adj, ops);
+    ops.push_back(TailOp{TO_PROLONG, rel, 0, 0});
+    for (int k = 0; k < h->opt.nu2; ++k) relax();
+}
+
+struct ImageBuf {
+    std::vector<unsigned char> b;
+    int put(const void *p, size_t n)
+    {
+        const size_t o = (b.size() + 15) & ~size_t(15);
+        b.resize(o + n);
+        if (n) std::memcpy(&b[o], p, n);
+        return (int)o;
+    }
+};
+
+size_t align16(size_t n) { return (n + 15) & ~size_t(15); }
+
+// Builds the LDS image of levels lt .. nlev-1 for type T and direction adj;
+// returns the LDS bytes the kernel needs (image + u, f + scratch).
+template <typename T>
+size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char> &img, TailPlan<T> &plan)
+{
+    const int nt = h->nlev - lt, dim = h->grid.dim;
+    std::vector<TailOp> ops;
+    tail_ops_rec(h, lt, lt, adj, ops);
+    ImageBuf I;
+    std::vector<TailLevel> tl(nt);
+    std::memset(tl.data(), 0, tl.size() * sizeof(TailLevel));
+    plan.lev_off = I.put(tl.data(), tl.size() * sizeof(TailLevel));
+    plan.ops_off = I.put(ops.data(), ops.size() * sizeof(TailOp));
+    plan.nops = (int)ops.size();
+    for (int r = 0; r < nt; ++r) {
+        const Level &L = h->lev[lt + r];
+        TailLevel &t = tl[r];
+        t.d = L.d;
+        {
+            const std::vector<T> vt(L.hblk[adj].begin(), L.hblk[adj].end());
+            t.co = I.put(vt.data(), vt.size() * sizeof(T));
+            t.cs = (int)L.cs;
+        }
+        if (lt + r == h->nlev - 1) continue;
+        for (int sl = 0; sl < 2; ++sl)
+            for (int c = 0; c < 2; ++c) {
+                if (h->slot_motif[sl] < 0) continue;
+                const HostTable &ht = L.htab[sl][c];
+                const std::vector<NodeFac<double>> &f64 = L.hfac[sl][c][adj];
+                std::vector<NodeFac<T>> fv(f64.size());
+                for (size_t q = 0; q < f64.size(); ++q)
+                    fv[q] = NodeFac<T>{(T)f64[q].alpha, (T)f64[q].inv, (T)f64[q].gam, (T)f64[q].z};
+                t.chunk_off[sl][c] = I.put(ht.chunks.data(), ht.chunks.size() * sizeof(Chunk));
+                t.block_off[sl][c] = I.put(ht.blocks.data(), ht.blocks.size() * sizeof(Block));
+                t.wg_off[sl][c] = I.put(ht.wgs.data(), ht.wgs.size() * sizeof(WGDesc));
+                t.fac_off[sl][c] = I.put(fv.data(), fv.size() * sizeof(NodeFac<T>));
+                t.nwg[sl][c] = (int)ht.wgs.size();
+                for (const Block &bk : ht.blocks)
+                    if (bk.type == BT_RING) t.rings[sl][c] = 1;
+            }
+    }
+    size_t off = align16(I.b.size());
+    plan.image_bytes = (int)off;
+    for (int r = 0; r < nt; ++r) {
+        const size_t nb = align16((size_t)h->lev[lt + r].d.nn * sizeof(T));
+        tl[r].uoff = (int)off;
+        off += nb;
+        tl[r].foff = (int)off;
+        off += nb;
+    }
+    plan.rhs_off = (int)off;
+    off += align16((size_t)h->nunk_coarse * sizeof(T));
+    std::memcpy(&I.b[plan.lev_off], tl.data(), tl.size() * sizeof(TailLevel));
+    I.b.resize(plan.image_bytes, 0);
+    img.swap(I.b);
+    plan.nunk = h->nunk_coarse;
+    plan.dim = dim;
+    plan.nn0 = h->lev[lt].d.nn;
+    return off;
+}
+
+void free_tail(mg_handle *h)
+{
+    for (auto &row : h->tail_img)
+        for (void *&p : row) {
+            if (p) (void)hipFree(p);
+            p = nullptr;
+        }
+    h->tail_lv = -1;
+}
+
+int build_tail(mg_handle *h)
+{
+    if (h->pool.host_only) return MG_OK;
+    const int key[4] = {h->checker ? 1 : 0, h->opt.nu1, h->opt.nu2, h->opt.gamma};
+    if (std::equal(key, key + 4, h->tail_key)) return MG_OK;
+    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
+    free_tail(h);
+    std::copy(key, key + 4, h->tail_key);
+    const char *env = std::getenv("TWMG_NO_TAIL");
+    if (env && env[0] == '1') return MG_OK;
+    const int nl = h->nlev;
+    int lt = -1;
+    for (int l = nl - 2; l >= 0; --l) {
+        bool fits = true;
+        for (int sl = 0; sl < 2; ++sl)
+            for (int c = 0; c < 2; ++c) fits = fits && h->lev[l].tab[sl][c].nwg_big == 0;
+        std::vector<unsigned char> img;
+        TailPlan<double> p;
+        if (!fits || tail_image<double>(h, l, 0, img, p) > (size_t)TAIL_BYTES) break;
+        lt = l;
+    }
+    if (lt < 0) return MG_OK;
+    for (int adj = 0; adj < 2; ++adj) {
+        std::vector<unsigned char> i64, i32;
+        tail_image<double>(h, lt, adj, i64, h->tail64[adj]);
+        tail_image<float>(h, lt, adj, i32, h->tail32[adj]);
+        const std::vector<unsigned char> *src[2] = {&i64, &i32};
+        for (int k = 0; k < 2; ++k) {
+            void *p = nullptr;
+            if (hipMalloc(&p, src[k]->size()) != hipSuccess) return MG_ENOMEM;
+            h->tail_img[k][adj] = p;
+            HIPCHK(hipMemcpy(p, src[k]->data(), src[k]->size(), hipMemcpyHostToDevice));
+        }
+        h->tail64[adj].image = (const unsigned char *)h->tail_img[0][adj];
+        h->tail32[adj].image = (const unsigned char *)h->tail_img[1][adj];
+    }
+    h->tail_lv = lt;
+    return MG_OK;
+}
+
 int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const mg_options *opt)
 {
     if (grid->dim != 2 && grid->dim != 3) return MG_EINVAL;
@@ -890,52 +1054,40 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         for (int a = 0; a < dim; ++a) cur[a] /= 2;
     }
     h->nlev = nl;
-    // coefficient arrays: forward and transposed, FP64 and FP32
+    // coefficient blocks: forward and transposed, FP64 and FP32.  The
+    // transposed operator's row p has the forward coefficients of its
+    // neighbours toward p: lo^T_i = hi_{i-1}, hi^T_i = lo_{i+1}.
     for (int l = 0; l < nl; ++l) {
         Level &L = h->lev[l];
-        for (int a = 0; a < 3; ++a) {
-            const int n = a < dim ? L.d.n[a] : 0;
-            std::vector<double> lo(n + 1, 0.0), hi(n + 1, 0.0), dg(n + 1, 0.0), loT(n + 1, 0.0), hiT(n + 1, 0.0);
-            if (a < dim) {
-                lo = L.lo[a];
-                hi = L.hi[a];
-                for (int i = 1; i < n; ++i) {
-                    dg[i] = -(lo[i] + hi[i]);
-                    loT[i] = (i - 1 >= 1) ? hi[i - 1] : 0.0;
-                    hiT[i] = (i + 1 <= n - 1) ? lo[i + 1] : 0.0;
-                }
+        long long cs = 1;
+        for (int a = 0; a < dim; ++a) cs = std::max(cs, (long long)L.d.n[a] + 1);
+        L.cs = cs;
+        for (int o = 0; o < 2; ++o) L.hblk[o].assign(9 * cs, 0.0);
+        for (int a = 0; a < dim; ++a) {
+            const int n = L.d.n[a];
+            const std::vector<double> &lo = L.lo[a], &hi = L.hi[a];
+            for (int i = 0; i <= n; ++i) {
+                const bool in = i >= 1 && i <= n - 1;
+                const double dg = in ? -(lo[i] + hi[i]) : 0.0;
+                L.hblk[0][(2 * a) * cs + i] = lo[i];
+                L.hblk[0][(2 * a + 1) * cs + i] = hi[i];
+                L.hblk[0][(6 + a) * cs + i] = dg;
+                L.hblk[1][(2 * a) * cs + i] = (in && i - 1 >= 1) ? hi[i - 1] : 0.0;
+                L.hblk[1][(2 * a + 1) * cs + i] = (in && i + 1 <= n - 1) ? lo[i + 1] : 0.0;
+                L.hblk[1][(6 + a) * cs + i] = dg;
             }
-            L.hco[0][0][a] = lo;
-            L.hco[0][1][a] = hi;
-            L.hco[0][2][a] = dg;
-            L.hco[1][0][a] = loT;
-            L.hco[1][1][a] = hiT;
-            L.hco[1][2][a] = dg;
-            std::vector<float> lo32(lo.begin(), lo.end()), hi32(hi.begin(), hi.end()), dg32(dg.begin(), dg.end()),
-                loT32(loT.begin(), loT.end()), hiT32(hiT.begin(), hiT.end());
-            int err = 0;
-            L.c64[0].lo[a] = h->pool.upload(lo, err);
-            L.c64[0].hi[a] = h->pool.upload(hi, err);
-            L.c64[0].dg[a] = h->pool.upload(dg, err);
-            L.c64[1].lo[a] = h->pool.upload(loT, err);
-            L.c64[1].hi[a] = h->pool.upload(hiT, err);
-            L.c64[1].dg[a] = L.c64[0].dg[a];
-            L.c32[0].lo[a] = h->pool.upload(lo32, err);
-            L.c32[0].hi[a] = h->pool.upload(hi32, err);
-            L.c32[0].dg[a] = h->pool.upload(dg32, err);
-            L.c32[1].lo[a] = h->pool.upload(loT32, err);
-            L.c32[1].hi[a] = h->pool.upload(hiT32, err);
-            L.c32[1].dg[a] = L.c32[0].dg[a];
+        }
+        int err = 0;
+        for (int o = 0; o < 2; ++o) {
+            const std::vector<float> b32(L.hblk[o].begin(), L.hblk[o].end());
+            const double *p64 = h->pool.upload(L.hblk[o], err);
+            const float *p32 = h->pool.upload(b32, err);
             if (err) return err;
+            L.c64[o] = make_coef<double>(p64, cs);
+            L.c32[o] = make_coef<float>(p32, cs);
+            L.hc64[o] = make_coef<double>(L.hblk[o].data(), cs);
         }
     }
-    for (int l = 0; l < nl; ++l)
-        for (int o = 0; o < 2; ++o)
-            for (int a = 0; a < 3; ++a) {
-                h->lev[l].hc64[o].lo[a] = h->lev[l].hco[o][0][a].data();
-                h->lev[l].hc64[o].hi[a] = h->lev[l].hco[o][1][a].data();
-                h->lev[l].hc64[o].dg[a] = h->lev[l].hco[o][2][a].data();
-            }
     // block tables for every level that is smoothed
     for (int l = 0; l + 1 < nl; ++l) {
         Level &L = h->lev[l];
@@ -1018,6 +1170,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         if (err) return err;
         if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double)));
     }
+    if ((rc = build_tail(h))) return rc;
     h->ws_bytes = workspace_layout(h, false);
     return MG_OK;
 }
@@ -1060,10 +1213,23 @@ template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
     return MG_OK;
 }
 
+template <typename T> TailPlan<T> tail_plan(const mg_handle *h, int adj)
+{
+    TailPlan<T> p;
+    if constexpr (sizeof(T) == 8) p = h->tail64[adj];
+    else p = h->tail32[adj];
+    p.ainv = cinv<T>(h, adj);
+    return p;
+}
+
 template <typename T> int cycle(mg_handle *h, int lv, T *u, const T *f, int adj)
 {
     Level &L = h->lev[lv];
     const int B = h->grid.batch;
+    if (lv == h->tail_lv) {
+        HIPCHK(launch_tail_cycle<T>(tail_plan<T>(h, adj), u, f, B, h->stream));
+        return MG_OK;
+    }
     if (lv == h->nlev - 1) {
         HIPCHK(launch_coarse_solve<T>(L.d, coefs<T>(L, adj), u, f, cinv<T>(h, adj), h->nunk_coarse, B, h->stream));
         return MG_OK;
@@ -1184,6 +1350,7 @@ void mg_destroy(mg_handle *h)
     else (void)hipDeviceSynchronize();
     if (h->ws_owned && h->ws) (void)hipFree(h->ws);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
+    free_tail(h);
     delete h;
 }
 
@@ -1206,7 +1373,7 @@ int mg_set_options(mg_handle *h, const mg_options *opt)
     if (!ck && (m0 != h->slot_motif[0] || m1 != h->slot_motif[1])) return MG_EINVAL;
     h->opt = *opt;
     h->checker = ck;
-    return MG_OK;
+    return build_tail(h);
 }
 
 size_t mg_workspace_bytes(const mg_handle *h) { return h ? h->ws_bytes : 0; }
@@ -1426,9 +1593,11 @@ int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int n
                                                                  : point_rhs<double, 3>(L.d, c, ub, fb, chs[ln], k);
                         for (int ln = 0; ln < w.nchunk; ++ln) {
                             if (L.d.dim == 2)
-                                sweep_phase1<double, 2, false, true>(L.d, c, &pt[ln * CH], chs[ln], ln, r, st[ln]);
+                                sweep_phase1<double, 2, false, true>(L.d, c, [&](int k) { return pt[ln * CH + k]; }, pt[ln * CH + chs[ln].len - 1],
+                                                                    chs[ln], ln, r, st[ln]);
                             else
-                                sweep_phase1<double, 3, false, true>(L.d, c, &pt[ln * CH], chs[ln], ln, r, st[ln]);
+                                sweep_phase1<double, 3, false, true>(L.d, c, [&](int k) { return pt[ln * CH + k]; }, pt[ln * CH + chs[ln].len - 1],
+                                                                    chs[ln], ln, r, st[ln]);
                         }
                         for (int ln = 0; ln < w.nchunk; ++ln) rhs[ln] = r.rs[ln] + r.rn[ln];
                         reduced_solve_seq<double>(w.nchunk, &t.chunks[w.chunk0], &fac[w.chunk0], rhs.data(),

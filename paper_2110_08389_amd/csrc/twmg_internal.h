@@ -91,11 +91,31 @@ struct Dims {
     long long nn;      // nodes per problem
 };
 
+// Coefficients of one level (one direction of the operator), stored as nine
+// arrays of cs entries in one block: lo_x, hi_x, lo_y, hi_y, lo_z, hi_z, dg_x,
+// dg_y, dg_z, each indexed by the node coordinate along its axis.  The array of
+// direction d (= 2*axis + positive) starts at base + d*cs, so picking one for a
+// per-lane direction is address arithmetic, not a choice between pointers.
 template <typename T> struct Coef {
-    const T *lo[3];    // coefficient toward the -1 neighbour, indexed by the node coordinate
+    const T *lo[3];    // coefficient toward the -1 neighbour
     const T *hi[3];    // toward the +1 neighbour
     const T *dg[3];    // contribution of the axis to the diagonal
+    const T *base;     // start of the block (== lo[0])
+    long long cs;      // entries per array
 };
+
+template <typename T> __host__ __device__ inline Coef<T> make_coef(const T *base, long long cs)
+{
+    Coef<T> c;
+    for (int a = 0; a < 3; ++a) {
+        c.lo[a] = base + (2 * a) * cs;
+        c.hi[a] = base + (2 * a + 1) * cs;
+        c.dg[a] = base + (6 + a) * cs;
+    }
+    c.base = base;
+    c.cs = cs;
+    return c;
+}
 
 struct SweepTable {
     Chunk *chunks = nullptr;
@@ -106,6 +126,47 @@ struct SweepTable {
     int nwg = 0, nchunk = 0, nblock = 0;
     int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others at most NT/2
     bool rings = false;
+};
+
+// ---- coarse-level cycle in one workgroup ---------------------------------
+// The coarsest levels of the hierarchy are small enough to live in LDS: one
+// workgroup per problem runs their whole sub-cycle (smoothing, defect
+// restriction, coarsest solve, prolongation) from a host-built list of
+// operations, with workgroup barriers between them.  Its read-only data (level
+// descriptors, coefficients, block tables, operations) form one image that the
+// kernel copies into LDS; all offsets below are byte offsets into LDS.
+constexpr int TAIL_BYTES = 147456; // LDS bytes for the image plus the levels' u, f and solve scratch
+constexpr int TAIL_NT = NT / 2;    // lanes of the coarse-level workgroup
+
+enum TailOpKind : uint8_t { TO_SWEEP = 0, TO_CHECKER = 1, TO_RESTRICT = 2, TO_PROLONG = 3, TO_SOLVE = 4 };
+struct TailOp {
+    uint8_t kind;   // TailOpKind
+    uint8_t lv;     // level, counted from the first level of the tail
+    uint8_t slot;   // TO_SWEEP: motif slot
+    uint8_t colour; // TO_SWEEP / TO_CHECKER
+};
+
+struct TailLevel {
+    Dims d;
+    int co;            // coefficient block (nine arrays of cs entries, as in Coef)
+    int cs;
+    int uoff, foff;    // the level's u and f (whole node arrays)
+    int chunk_off[2][2], block_off[2][2], wg_off[2][2], fac_off[2][2]; // [slot][colour] block tables
+    int nwg[2][2];
+    int rings[2][2];
+};
+
+template <typename T> struct TailPlan {
+    const unsigned char *image = nullptr; // device copy of the read-only image (16-byte multiple)
+    int image_bytes = 0;
+    int lev_off = 0;                      // TailLevel array
+    int ops_off = 0;                      // TailOp array
+    int nops = 0;
+    int rhs_off = 0;                      // coarsest solve scratch (nunk values)
+    int nunk = 0;                         // unknowns of the coarsest level
+    int dim = 2;
+    long long nn0 = 0;                    // nodes of the first tail level (batch stride)
+    const T *ainv = nullptr;              // coarsest-level inverse (global memory)
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
@@ -135,6 +196,9 @@ hipError_t launch_set_boundary(const Dims &d, double *u, const double *bc, int z
 template <typename T> hipError_t launch_fill(T *p, long long n, T v, hipStream_t s);
 hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *lam, const double *w, double *g,
                           int batch, hipStream_t s);
+
+template <typename T>
+hipError_t launch_tail_cycle(const TailPlan<T> &p, T *u, const T *f, int batch, hipStream_t s);
 
 constexpr int NORM_PARTS = 1024;  // partial-maximum slots used by launch_resnorm
 
