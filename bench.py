@@ -72,10 +72,12 @@ def main():
     if args.calibrate_copy:
         # a plain copy of known size: FETCH_SIZE and WRITE_SIZE of its kernel
         # should each read 512 MiB; their ratio to that is the counter scale
+        # an elementwise kernel (reads a, writes b once each), not the runtime's
+        # copy engine path, so the counters see ordinary vector loads and stores
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 8}))
         return

@@ -166,7 +166,7 @@ int mg_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjo
 int mg_residual(mg_handle *h, int lv, const double *u, const double *f, double *d, int adjoint);
 int mg_residual_restrict(mg_handle *h, int lv, const double *u, const double *f, double *fc, double *uc, int adjoint);
 int mg_prolong_add(mg_handle *h, int lv, const double *ec, double *u);
-/* FP32 versions of mg_smooth and mg_residual_restrict (used inside refinement). */
+/* FP32 version of mg_smooth (the smoother used inside refinement cycles; u and f are FP32 node arrays). */
 int mg_smooth_f32(mg_handle *h, int lv, float *u, const float *f, int nu, int adjoint);
 
 const char *mg_strerror(int code);
