@@ -169,6 +169,28 @@ int mg_prolong_add(mg_handle *h, int lv, const double *ec, double *u);
 /* FP32 version of mg_smooth (the smoother used inside refinement cycles; u and f are FP32 node arrays). */
 int mg_smooth_f32(mg_handle *h, int lv, float *u, const float *f, int nu, int adjoint);
 
+/* Device layout.  Internally each level keeps its arrays in a layout chosen
+ * for its smoother: on the large 2D levels of the tweed, wireframe and
+ * y-zebra smoothers, the nodes whose block lines run along y (Section 3: the
+ * lines are orthogonal to the nearest wall for tweed, parallel to it for
+ * wireframe) sit in a second, column-major plane, so that every line is
+ * contiguous; elsewhere the layout is the row-major one above.  The calls
+ * above convert on entry and exit.  A caller that keeps data in the device
+ * layout between calls uses these:
+ * mg_level_array_len: number of elements of one problem's array of level lv
+ *   in the device layout (the batch stride); *len is a host pointer.
+ * mg_to_layout / mg_from_layout: row-major <-> device layout (all problems of
+ *   the batch); src and dst must not overlap.
+ * mg_half_sweep: one half-sweep -- every block of one colour (0 red, 1 black)
+ *   of motif slot `slot` (0, or 1 for the second motif of an alternating
+ *   smoother) solved exactly with the other colour frozen -- on arrays in the
+ *   device layout.  MG_EINVAL for the checkerboard smoother or a slot the
+ *   smoother does not have. */
+int mg_level_array_len(const mg_handle *h, int lv, long long *len);
+int mg_to_layout(mg_handle *h, int lv, const double *src, double *dst);
+int mg_from_layout(mg_handle *h, int lv, const double *src, double *dst);
+int mg_half_sweep(mg_handle *h, int lv, double *u, const double *f, int slot, int colour, int adjoint);
+
 const char *mg_strerror(int code);
 
 #ifdef __cplusplus

@@ -31,6 +31,13 @@ int mg_debug_setup_host(const mg_grid *grid, const mg_stretching *stretch, const
  * checkerboard smoother (it has no tables). */
 int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint);
 
+/* As mg_debug_host_smooth, but the per-lane steps address the arrays in the
+ * level's own device layout (for the large levels of the tweed, wireframe and
+ * y-zebra smoothers, two planes: the points of lines along x row-major, those
+ * of lines along y column-major).  u and f are given and returned row-major;
+ * the hook converts them on the host. */
+int mg_debug_host_smooth_layout(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,12 +72,17 @@ _SIGS = [
     ("mg_residual_restrict", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int],
      C.c_int),
     ("mg_prolong_add", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    ("mg_level_array_len", [C.c_void_p, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
+    ("mg_to_layout", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    ("mg_from_layout", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    ("mg_half_sweep", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
     ("mg_strerror", [C.c_int], C.c_char_p),
     # test hooks (include/twmg_debug.h)
     ("mg_debug_table_info", [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
     ("mg_debug_setup_host", [C.POINTER(mg_grid), C.POINTER(mg_stretching), C.POINTER(mg_options),
                              C.POINTER(C.c_void_p)], C.c_int),
     ("mg_debug_host_smooth", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
+    ("mg_debug_host_smooth_layout", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
 ]
 ENTRY_POINTS = [s[0] for s in _SIGS]
 
@@ -278,6 +283,35 @@ class Solver:
     def prolong_add(self, ec, u, lv=0):
         _check(capi().mg_prolong_add(self.h, lv, self._arg(ec, lv + 1), self._arg(u, lv)), "mg_prolong_add")
         return u
+
+    # -- device layout (see mg_level_array_len in include/twmg.h) -------------
+    def array_len(self, lv=0):
+        n = C.c_longlong()
+        _check(capi().mg_level_array_len(self.h, lv, C.byref(n)), "mg_level_array_len")
+        return n.value
+
+    def to_layout(self, x, lv=0):
+        """Row-major node array(s) of level lv -> a flat tensor in the level's device layout."""
+        out = self.torch.zeros(self.batch * self.array_len(lv), dtype=self.torch.float64, device=self.device)
+        _check(capi().mg_to_layout(self.h, lv, self._arg(x, lv), _ptr(out)), "mg_to_layout")
+        return out
+
+    def from_layout(self, xd, lv=0):
+        out = self.zeros(lv)
+        if xd.numel() != self.batch * self.array_len(lv) or xd.dtype != self.torch.float64 or xd.device != self.device:
+            raise ValueError("from_layout: expected a float64 device tensor of batch * array_len(lv) elements")
+        _check(capi().mg_from_layout(self.h, lv, _ptr(xd.contiguous()), _ptr(out)), "mg_from_layout")
+        return out
+
+    def half_sweep(self, ud, fd, colour, lv=0, slot=0, adjoint=False):
+        """One half-sweep (one colour) on device-layout arrays from to_layout."""
+        n = self.batch * self.array_len(lv)
+        for t in (ud, fd):
+            if t.numel() != n or t.dtype != self.torch.float64 or t.device != self.device or not t.is_contiguous():
+                raise ValueError("half_sweep: expected contiguous float64 device tensors in the device layout")
+        _check(capi().mg_half_sweep(self.h, lv, _ptr(ud), _ptr(fd), int(slot), int(colour), int(adjoint)),
+               "mg_half_sweep")
+        return ud
 
 
 def _autograd():

@@ -11,19 +11,41 @@ namespace twmg {
 // small helpers
 // ---------------------------------------------------------------------------
 
-// defect f - L u at interior node (i, j, l) with linear index p
+// slots of interior node (i, j, l) and of its neighbours x-, x+, y-, y+, z-, z+
+template <int DIM> struct Stencil {
+    long long p, nb[2 * DIM];
+};
+template <int DIM> __device__ __forceinline__ Stencil<DIM> stencil_at(const Dims &d, int i, int j, int l)
+{
+    Stencil<DIM> s;
+    if (DIM == 2 && d.layout != LAYOUT_ROW) {
+        s.p = nidx(d, i, j, 0);
+        s.nb[0] = nidx(d, i - 1, j, 0);
+        s.nb[1] = nidx(d, i + 1, j, 0);
+        s.nb[2] = nidx(d, i, j - 1, 0);
+        s.nb[3] = nidx(d, i, j + 1, 0);
+    } else {
+        s.p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+#pragma unroll
+        for (int dd = 0; dd < 2 * DIM; ++dd) s.nb[dd] = s.p + dir_off(d, dd);
+    }
+    return s;
+}
+
+// defect f - L u at interior node (i, j, l)
 template <typename T, int DIM>
 __device__ __forceinline__ T defect_at(const Dims &d, const Coef<T> &cf, const T *__restrict__ u,
-                                       const T *__restrict__ f, int i, int j, int l, long long p)
+                                       const T *__restrict__ f, int i, int j, int l)
 {
-    T s = cf.lo[0][i] * u[p - 1] + cf.hi[0][i] * u[p + 1];
-    s += cf.lo[1][j] * u[p - d.st[1]] + cf.hi[1][j] * u[p + d.st[1]];
+    const Stencil<DIM> q = stencil_at<DIM>(d, i, j, l);
+    T s = cf.lo[0][i] * u[q.nb[0]] + cf.hi[0][i] * u[q.nb[1]];
+    s += cf.lo[1][j] * u[q.nb[2]] + cf.hi[1][j] * u[q.nb[3]];
     T dg = cf.dg[0][i] + cf.dg[1][j];
     if (DIM == 3) {
-        s += cf.lo[2][l] * u[p - d.st[2]] + cf.hi[2][l] * u[p + d.st[2]];
+        s += cf.lo[2][l] * u[q.nb[4]] + cf.hi[2][l] * u[q.nb[5]];
         dg += cf.dg[2][l];
     }
-    return f[p] - (s + dg * u[p]);
+    return f[q.p] - (s + dg * u[q.p]);
 }
 
 template <int DIM> __device__ __forceinline__ bool interior(const Dims &d, int i, int j, int l)
@@ -33,10 +55,53 @@ template <int DIM> __device__ __forceinline__ bool interior(const Dims &d, int i
     return in;
 }
 
-// rows of a node array: (j, l) pairs; row r -> j = r % (ny+1), l = r / (ny+1)
+// rows of a row-major node array: (j, l) pairs; row r -> j = r % (ny+1), l = r / (ny+1)
 __device__ __forceinline__ int nrows(const Dims &d, int DIM)
 {
     return (d.n[1] + 1) * (DIM == 3 ? d.n[2] + 1 : 1);
+}
+
+// Storage-order traversal of a node array, so that consecutive threads touch
+// consecutive slots: LAYOUT_ROW has the rows (j, l) of nx+1 nodes; a split
+// layout has the ny+1 rows of plane R, then the nx+1 columns (ny+1 nodes) of
+// plane C.
+__device__ __forceinline__ int lrows(const Dims &d, int DIM)
+{
+    return d.layout == LAYOUT_ROW ? nrows(d, DIM) : (d.n[1] + 1) + (d.n[0] + 1);
+}
+__device__ __forceinline__ int lrow_len(const Dims &d, int row)
+{
+    return (d.layout != LAYOUT_ROW && row > d.n[1]) ? d.n[1] + 1 : d.n[0] + 1;
+}
+// node q of row `row`: its coordinates and slot; false when the node is kept
+// in the other plane (each node is visited exactly once over all rows)
+template <int DIM>
+__device__ __forceinline__ bool lnode(const Dims &d, int row, int q, int &i, int &j, int &l, long long &p)
+{
+    if (d.layout == LAYOUT_ROW) {
+        j = row % (d.n[1] + 1);
+        l = DIM == 3 ? row / (d.n[1] + 1) : 0;
+        i = q;
+        p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+        return true;
+    }
+    l = 0;
+    if (row <= d.n[1]) {
+        j = row;
+        i = q;
+        p = i + j * d.st[1];
+        return !col_plane(d, i, j);
+    }
+    i = row - (d.n[1] + 1);
+    j = q;
+    p = d.nn + j + (long long)i * (d.n[1] + 1);
+    return col_plane(d, i, j);
+}
+
+static int lrow_grid(const Dims &d)
+{
+    const int r = d.layout == LAYOUT_ROW ? (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1) : d.n[0] + d.n[1] + 2;
+    return r < 65535 ? r : 65535;
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +249,7 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
 // The work of one workgroup descriptor w; ub / fb may point to global memory
 // or to LDS (the coarse-level kernel keeps its levels there).  All NT lanes of
 // the workgroup must call it.
-template <typename T, int DIM, int NT>
+template <typename T, int DIM, int NT, bool DOFF>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
                                          const Block *__restrict__ blocks, const WGDesc w,
@@ -234,7 +299,8 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         ext = ch.ext;
         nf = fac[w.chunk0 + t];
         const T *rp = &s_pt[t * PS];
-        sweep_phase1<T, DIM, false, true>(d, cf, [&](int k) { return rp[k]; }, rp[ch.len - 1], ch, t, red, st);
+        sweep_phase1<T, DIM, false, true, DOFF>(d, cf, [&](int k) { return rp[k]; }, rp[ch.len - 1], ch, t, red,
+                                                st);
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
@@ -249,17 +315,18 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     }
 }
 
-template <typename T, int DIM, int NT>
+// DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients)
+template <typename T, int DIM, int NT, bool DOFF>
 __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
                                                     const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
                                                     int rings)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
-    sweep_wg<T, DIM, NT>(d, cf, u + boff, f + boff, chunks, blocks, wgs[blockIdx.x], fac, rings);
+    const long long boff = (long long)blockIdx.y * d.bs;
+    sweep_wg<T, DIM, NT, DOFF>(d, cf, u + boff, f + boff, chunks, blocks, wgs[blockIdx.x], fac, rings);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool DOFF>
 static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
                              const NodeFac<T> *fac, int batch, hipStream_t s)
 {
@@ -268,11 +335,11 @@ static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, 
     // with NT lanes; the rest run with NT/2 lanes (a third of the LDS), so that
     // several workgroups share a CU and hide each other's memory waits
     if (tab.nwg_big > 0)
-        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
                            tab.chunks, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big)
-        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2), 0, s,
-                           d, c, u, f, tab.chunks, tab.blocks, tab.wgs + tab.nwg_big, fac, rings);
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2),
+                           0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs + tab.nwg_big, fac, rings);
 }
 
 template <typename T>
@@ -283,8 +350,14 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
     const NodeFac<T> *fac;
     if constexpr (sizeof(T) == 8) fac = tab.fac64[adj];
     else fac = tab.fac32[adj];
-    if (d.dim == 2) launch_sweep_dim<T, 2>(d, c, u, f, tab, fac, batch, s);
-    else launch_sweep_dim<T, 3>(d, c, u, f, tab, fac, batch, s);
+    const bool doff = sizeof(T) == 8 && adj == 0;
+    if (d.dim == 2) {
+        if (doff) launch_sweep_dim<T, 2, true>(d, c, u, f, tab, fac, batch, s);
+        else launch_sweep_dim<T, 2, false>(d, c, u, f, tab, fac, batch, s);
+    } else {
+        if (doff) launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, batch, s);
+        else launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, batch, s);
+    }
     return hipGetLastError();
 }
 
@@ -293,14 +366,14 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
 // red = (i + j [+ l]) even.
 // ---------------------------------------------------------------------------
 
-// point Gauss-Seidel value at interior node (i, j, l) with index p
+// point Gauss-Seidel value at interior node (i, j, l)
 template <typename T, int DIM>
-__device__ __forceinline__ T point_gs(const Dims &d, const Coef<T> &cf, const T *ub, const T *fb, int i, int j, int l,
-                                      long long p)
+__device__ __forceinline__ T point_gs(const Dims &d, const Coef<T> &cf, const T *ub, const T *fb, int i, int j, int l)
 {
-    T s = fb[p] - cf.lo[0][i] * ub[p - 1] - cf.hi[0][i] * ub[p + 1] - cf.lo[1][j] * ub[p - d.st[1]] -
-          cf.hi[1][j] * ub[p + d.st[1]];
-    if (DIM == 3) s -= cf.lo[2][l] * ub[p - d.st[2]] + cf.hi[2][l] * ub[p + d.st[2]];
+    const Stencil<DIM> q = stencil_at<DIM>(d, i, j, l);
+    T s = fb[q.p] - cf.lo[0][i] * ub[q.nb[0]] - cf.hi[0][i] * ub[q.nb[1]] - cf.lo[1][j] * ub[q.nb[2]] -
+          cf.hi[1][j] * ub[q.nb[3]];
+    if (DIM == 3) s -= cf.lo[2][l] * ub[q.nb[4]] + cf.hi[2][l] * ub[q.nb[5]];
     return s / diag_at<T, DIM>(cf, i, j, l);
 }
 
@@ -308,22 +381,22 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_checker(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                  int colour)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
+    const long long boff = (long long)blockIdx.y * d.bs;
     T *ub = u + boff;
     const T *fb = f + boff;
-    const int rows = nrows(d, DIM);
+    const int rows = lrows(d, DIM);
     for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-        const int j = r % (d.n[1] + 1), l = r / (d.n[1] + 1);
-        if (j == 0 || j == d.n[1] || (DIM == 3 && (l == 0 || l == d.n[2]))) continue;
-        const int i0 = 1 + ((1 + j + l + colour) & 1);
-        for (int i = i0 + 2 * threadIdx.x; i < d.n[0]; i += 2 * blockDim.x) {
-            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
-            ub[p] = point_gs<T, DIM>(d, cf, ub, fb, i, j, l, p);
+        const int len = lrow_len(d, r);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(d, r, q, i, j, l, p) || !interior<DIM>(d, i, j, l) || ((i + j + l) & 1) != colour) continue;
+            ub[p] = point_gs<T, DIM>(d, cf, ub, fb, i, j, l);
         }
     }
 }
 
-static int row_grid(const Dims &d) { int r = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1); return r < 65535 ? r : 65535; }
+static int row_grid(const Dims &d) { return lrow_grid(d); }
 
 template <typename T>
 hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s)
@@ -337,27 +410,32 @@ hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int
 // ---------------------------------------------------------------------------
 // Defect d = f - L u (Section 4 step 3), 0 on boundary nodes.
 // ---------------------------------------------------------------------------
+// r has its own layout (dout): the caller's row-major array or the level's
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_residual(Dims d, Coef<T> cf, const T *__restrict__ u,
+__global__ void __launch_bounds__(256) k_residual(Dims d, Dims dout, Coef<T> cf, const T *__restrict__ u,
                                                   const T *__restrict__ f, T *__restrict__ r)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
-    const int rows = nrows(d, DIM);
+    const long long boff = (long long)blockIdx.y * d.bs, roff = (long long)blockIdx.y * dout.bs;
+    const int rows = lrows(d, DIM);
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
-        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
-            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
-            r[boff + p] = interior<DIM>(d, i, j, l) ? defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l, p) : T(0);
+        const int len = lrow_len(d, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(d, row, q, i, j, l, p)) continue;
+            r[roff + nidx(dout, i, j, l)] =
+                interior<DIM>(d, i, j, l) ? defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l) : T(0);
         }
     }
 }
 
 template <typename T>
-hipError_t launch_residual(const Dims &d, const Coef<T> &c, const T *u, const T *f, T *r, int batch, hipStream_t s)
+hipError_t launch_residual(const Dims &d, const Dims &dout, const Coef<T> &c, const T *u, const T *f, T *r, int batch,
+                           hipStream_t s)
 {
     dim3 grid(row_grid(d), batch);
-    if (d.dim == 2) hipLaunchKernelGGL((k_residual<T, 2>), grid, dim3(256), 0, s, d, c, u, f, r);
-    else hipLaunchKernelGGL((k_residual<T, 3>), grid, dim3(256), 0, s, d, c, u, f, r);
+    if (d.dim == 2) hipLaunchKernelGGL((k_residual<T, 2>), grid, dim3(256), 0, s, d, dout, c, u, f, r);
+    else hipLaunchKernelGGL((k_residual<T, 3>), grid, dim3(256), 0, s, d, dout, c, u, f, r);
     return hipGetLastError();
 }
 
@@ -380,10 +458,7 @@ __device__ __forceinline__ T restrict_at(const Dims &fd, const Coef<T> &cf, cons
 #pragma unroll
             for (int a = -1; a <= 1; ++a) {
                 const int i = 2 * I + a, j = 2 * J + b, l = (DIM == 3) ? 2 * K + c : 0;
-                if (interior<DIM>(fd, i, j, l)) {
-                    const long long p = i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0);
-                    rowacc += w3[a + 1] * defect_at<T, DIM>(fd, cf, ub, fb, i, j, l, p);
-                }
+                if (interior<DIM>(fd, i, j, l)) rowacc += w3[a + 1] * defect_at<T, DIM>(fd, cf, ub, fb, i, j, l);
             }
             acc += (DIM == 3 ? w3[c + 1] : T(1)) * w3[b + 1] * rowacc;
         }
@@ -396,17 +471,18 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coe
                                                            const T *__restrict__ f, T *__restrict__ fc,
                                                            T *__restrict__ uc)
 {
-    const T *ub = u + (long long)blockIdx.y * fd.nn;
-    const T *fb = f + (long long)blockIdx.y * fd.nn;
-    const long long cboff = (long long)blockIdx.y * cd.nn;
-    const int rows = nrows(cd, DIM);
+    const T *ub = u + (long long)blockIdx.y * fd.bs;
+    const T *fb = f + (long long)blockIdx.y * fd.bs;
+    const long long cboff = (long long)blockIdx.y * cd.bs;
+    const int rows = lrows(cd, DIM);
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int J = row % (cd.n[1] + 1), K = row / (cd.n[1] + 1);
-        if (J == 0 || J == cd.n[1] || (DIM == 3 && (K == 0 || K == cd.n[2]))) continue;
-        for (int I = 1 + threadIdx.x; I < cd.n[0]; I += blockDim.x) {
-            const long long q = cboff + I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0);
-            fc[q] = restrict_at<T, DIM>(fd, cf, ub, fb, I, J, K);
-            uc[q] = T(0);
+        const int len = lrow_len(cd, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int I, J, K;
+            long long p;
+            if (!lnode<DIM>(cd, row, q, I, J, K, p) || !interior<DIM>(cd, I, J, K)) continue;
+            fc[cboff + p] = restrict_at<T, DIM>(fd, cf, ub, fb, I, J, K);
+            uc[cboff + p] = T(0);
         }
     }
 }
@@ -432,7 +508,7 @@ __device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int 
 {
     const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
     const int K0 = l >> 1, K1 = (l + 1) >> 1;
-    auto cval = [&](int I, int J, int K) -> T { return eb[I + J * cd.st[1] + (DIM == 3 ? K * cd.st[2] : 0)]; };
+    auto cval = [&](int I, int J, int K) -> T { return eb[nidx(cd, I, J, K)]; };
     T pl[2];
 #pragma unroll
     for (int kk = 0; kk < (DIM == 3 ? 2 : 1); ++kk) {
@@ -448,14 +524,17 @@ __device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
 {
-    T *ub = u + (long long)blockIdx.y * fd.nn;
-    const T *eb = ec + (long long)blockIdx.y * cd.nn;
-    const int rows = nrows(fd, DIM);
+    T *ub = u + (long long)blockIdx.y * fd.bs;
+    const T *eb = ec + (long long)blockIdx.y * cd.bs;
+    const int rows = lrows(fd, DIM);
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = row % (fd.n[1] + 1), l = row / (fd.n[1] + 1);
-        if (j == 0 || j == fd.n[1] || (DIM == 3 && (l == 0 || l == fd.n[2]))) continue;
-        for (int i = 1 + threadIdx.x; i < fd.n[0]; i += blockDim.x)
-            ub[i + j * fd.st[1] + (DIM == 3 ? l * fd.st[2] : 0)] += prolong_at<T, DIM>(cd, eb, i, j, l);
+        const int len = lrow_len(fd, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(fd, row, q, i, j, l, p) || !interior<DIM>(fd, i, j, l)) continue;
+            ub[p] += prolong_at<T, DIM>(cd, eb, i, j, l);
+        }
     }
 }
 
@@ -507,8 +586,8 @@ __global__ void __launch_bounds__(256) k_coarse_solve(Dims d, Coef<T> cf, T *__r
                                                       const T *__restrict__ ainv, int nunk)
 {
     __shared__ T rhs[1024];
-    T *ub = u + (long long)blockIdx.x * d.nn;
-    const T *fb = f + (long long)blockIdx.x * d.nn;
+    T *ub = u + (long long)blockIdx.x * d.bs;
+    const T *fb = f + (long long)blockIdx.x * d.bs;
     coarse_solve_wg<T, DIM>(d, cf, ub, fb, ainv, nunk, rhs);
 }
 
@@ -614,8 +693,7 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
             for (int q = threadIdx.x; q < nx * ny * nz; q += blockDim.x) {
                 const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = DIM == 3 ? 1 + q / (nx * ny) : 0;
                 if (((i + j + l) & 1) != op.colour) continue;
-                const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
-                us[p] = point_gs<T, DIM>(d, cf, us, fs, i, j, l, p);
+                us[i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0)] = point_gs<T, DIM>(d, cf, us, fs, i, j, l);
             }
         } else if (op.kind == TO_RESTRICT) {
             const TailLevel &C = lev[op.lv + 1];
@@ -689,16 +767,18 @@ template <typename T, int DIM, bool TO32>
 __global__ void __launch_bounds__(256) k_resnorm(Dims d, Coef<T> cf, const T *__restrict__ u, const T *__restrict__ f,
                                                  float *__restrict__ r32, double *__restrict__ partial)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
-    const int rows = nrows(d, DIM);
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int rows = lrows(d, DIM);
     double m = 0.0;
     bool nan = false;
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
-        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
-            const long long p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+        const int len = lrow_len(d, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(d, row, q, i, j, l, p)) continue;
             T r = 0;
-            if (interior<DIM>(d, i, j, l)) r = defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l, p);
+            if (interior<DIM>(d, i, j, l)) r = defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l);
             if (TO32) r32[boff + p] = (float)r;
             const double a = fabs((double)r);
             nan = nan || (a != a);
@@ -724,7 +804,7 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
 {
     int gx = npart / batch;
     if (gx < 1) return hipErrorInvalidValue;
-    const int rows = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1);
+    const int rows = lrow_grid(d);
     if (gx > rows) gx = rows;
     dim3 grid(gx, batch);
     if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<T, 2, false>), grid, dim3(256), 0, s, d, c, u, f, nullptr, partial);
@@ -738,7 +818,7 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
 {
     int gx = npart / batch;
     if (gx < 1) return hipErrorInvalidValue;
-    const int rows = (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1);
+    const int rows = lrow_grid(d);
     if (gx > rows) gx = rows;
     dim3 grid(gx, batch);
     if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<double, 2, true>), grid, dim3(256), 0, s, d, c, u, f, r32, partial);
@@ -750,14 +830,15 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
 // u += e at interior nodes (FP64 update of iterative refinement)
 template <int DIM> __global__ void __launch_bounds__(256) k_ir_update(Dims d, double *__restrict__ u, const float *__restrict__ e)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
-    const int rows = nrows(d, DIM);
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int rows = lrows(d, DIM);
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
-        if (j == 0 || j == d.n[1] || (DIM == 3 && (l == 0 || l == d.n[2]))) continue;
-        for (int i = 1 + threadIdx.x; i < d.n[0]; i += blockDim.x) {
-            const long long p = boff + i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
-            u[p] += (double)e[p];
+        const int len = lrow_len(d, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(d, row, q, i, j, l, p) || !interior<DIM>(d, i, j, l)) continue;
+            u[boff + p] += (double)e[boff + p];
         }
     }
 }
@@ -770,21 +851,24 @@ hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch,
     return hipGetLastError();
 }
 
-// boundary nodes <- bc (when given), interior <- 0 (when asked)
+// boundary nodes <- bc (when given; bc is a row-major node array), interior <- 0
+// (when asked); u has layout d.layout
 template <int DIM>
 __global__ void __launch_bounds__(256) k_set_boundary(Dims d, double *__restrict__ u, const double *__restrict__ bc,
                                                       int zero_interior)
 {
-    const long long boff = (long long)blockIdx.y * d.nn;
-    const int rows = nrows(d, DIM);
+    const long long boff = (long long)blockIdx.y * d.bs, bboff = (long long)blockIdx.y * d.nn;
+    const int rows = lrows(d, DIM);
     for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = row % (d.n[1] + 1), l = row / (d.n[1] + 1);
-        for (int i = threadIdx.x; i <= d.n[0]; i += blockDim.x) {
-            const long long p = boff + i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
+        const int len = lrow_len(d, row);
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            int i, j, l;
+            long long p;
+            if (!lnode<DIM>(d, row, q, i, j, l, p)) continue;
             if (interior<DIM>(d, i, j, l)) {
-                if (zero_interior) u[p] = 0.0;
+                if (zero_interior) u[boff + p] = 0.0;
             } else if (bc) {
-                u[p] = bc[p];
+                u[boff + p] = bc[bboff + i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0)];
             }
         }
     }
@@ -796,6 +880,61 @@ hipError_t launch_set_boundary(const Dims &d, double *u, const double *bc, int z
     dim3 grid(row_grid(d), batch);
     if (d.dim == 2) hipLaunchKernelGGL((k_set_boundary<2>), grid, dim3(256), 0, s, d, u, bc, zero_interior);
     else hipLaunchKernelGGL((k_set_boundary<3>), grid, dim3(256), 0, s, d, u, bc, zero_interior);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion between a row-major node array and a split layout through
+// 32 x 32 LDS tiles: the row-major side and plane R are accessed along rows,
+// plane C along its columns, so every access is contiguous.
+// ---------------------------------------------------------------------------
+template <typename T, bool TO_SPLIT>
+__global__ void __launch_bounds__(256) k_convert(Dims d, const T *__restrict__ src, T *__restrict__ dst)
+{
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const long long rb = (long long)blockIdx.z * d.nn, sb = (long long)blockIdx.z * d.bs;
+    const long long cst = d.n[1] + 1;
+    if (TO_SPLIT) {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + tx, j = j0 + r;
+            if (i <= d.n[0] && j <= d.n[1]) tile[r][tx] = src[rb + i + j * d.st[1]];
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + tx, j = j0 + r;
+            if (i <= d.n[0] && j <= d.n[1] && !col_plane(d, i, j)) dst[sb + i + j * d.st[1]] = tile[r][tx];
+        }
+        for (int c = ty; c < 32; c += 8) {
+            const int i = i0 + c, j = j0 + tx;
+            if (i <= d.n[0] && j <= d.n[1] && col_plane(d, i, j)) dst[sb + d.nn + j + i * cst] = tile[tx][c];
+        }
+    } else {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + tx, j = j0 + r;
+            if (i <= d.n[0] && j <= d.n[1] && !col_plane(d, i, j)) tile[r][tx] = src[sb + i + j * d.st[1]];
+        }
+        for (int c = ty; c < 32; c += 8) {
+            const int i = i0 + c, j = j0 + tx;
+            if (i <= d.n[0] && j <= d.n[1] && col_plane(d, i, j)) tile[tx][c] = src[sb + d.nn + j + i * cst];
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = i0 + tx, j = j0 + r;
+            if (i <= d.n[0] && j <= d.n[1]) dst[rb + i + j * d.st[1]] = tile[r][tx];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_convert(const Dims &d, const T *src, T *dst, int to_split, int batch, hipStream_t s)
+{
+    if (d.layout == LAYOUT_ROW)
+        return hipMemcpyAsync(dst, src, sizeof(T) * (size_t)d.nn * batch, hipMemcpyDeviceToDevice, s);
+    dim3 grid((d.n[0] + 32) / 32, (d.n[1] + 32) / 32, batch);
+    if (to_split) hipLaunchKernelGGL((k_convert<T, true>), grid, dim3(256), 0, s, d, src, dst);
+    else hipLaunchKernelGGL((k_convert<T, false>), grid, dim3(256), 0, s, d, src, dst);
     return hipGetLastError();
 }
 
@@ -865,8 +1004,9 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
     template hipError_t launch_block_sweep<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, int, \
                                               int, hipStream_t);                                                      \
     template hipError_t launch_checker<T>(const Dims &, const Coef<T> &, T *, const T *, int, int, hipStream_t);     \
-    template hipError_t launch_residual<T>(const Dims &, const Coef<T> &, const T *, const T *, T *, int,           \
-                                           hipStream_t);                                                              \
+    template hipError_t launch_residual<T>(const Dims &, const Dims &, const Coef<T> &, const T *, const T *, T *,  \
+                                           int, hipStream_t);                                                         \
+    template hipError_t launch_convert<T>(const Dims &, const T *, T *, int, int, hipStream_t);                      \
     template hipError_t launch_residual_restrict<T>(const Dims &, const Dims &, const Coef<T> &, const T *,          \
                                                     const T *, T *, T *, int, hipStream_t);                           \
     template hipError_t launch_prolong_add<T>(const Dims &, const Dims &, const T *, T *, int, hipStream_t);         \

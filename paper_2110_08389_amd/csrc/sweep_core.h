@@ -82,10 +82,8 @@ template <typename T> struct RedArrays {
 
 template <typename T> struct LaneState {
     T D[CH], G[CH], S[CH]; // interior elimination: delta, gamma, left spike
-    int L, sg, prev, cax;
+    int L, prev;
     bool hp;
-    long long p0, step;
-    const T *Pfwd;
 };
 
 // Right-hand side of point k of a chunk: f minus the couplings to every
@@ -99,7 +97,20 @@ __host__ __device__ __forceinline__ T point_rhs(const Dims &d, const Coef<T> &cf
     const bool hp = ch.flags & CF_PREV, hn = ch.flags & CF_NEXT, jn = ch.flags & CF_JUNCTION;
     const int ci = ch.c0[0] + (ax == 0 ? sg * k : 0), cj = ch.c0[1] + (ax == 1 ? sg * k : 0),
               cl = (DIM == 3) ? ch.c0[2] + (ax == 2 ? sg * k : 0) : 0;
-    const long long idx = ci + cj * d.st[1] + (DIM == 3 ? cl * d.st[2] : 0);
+    // slots of the point and of its 2*DIM neighbours (x-, x+, y-, y+, z-, z+)
+    long long nb[2 * DIM];
+    long long idx;
+    if (DIM == 2 && d.layout != LAYOUT_ROW) {
+        idx = nidx(d, ci, cj, 0);
+        nb[0] = nidx(d, ci - 1, cj, 0);
+        nb[1] = nidx(d, ci + 1, cj, 0);
+        nb[2] = nidx(d, ci, cj - 1, 0);
+        nb[3] = nidx(d, ci, cj + 1, 0);
+    } else {
+        idx = ci + cj * d.st[1] + (DIM == 3 ? cl * d.st[2] : 0);
+#pragma unroll
+        for (int dd = 0; dd < 2 * DIM; ++dd) nb[dd] = idx + dir_off(d, dd);
+    }
     unsigned inb = 0;
     if (k > 0 || hp) inb |= 1u << (ad ^ 1);
     if (k < L - 1) inb |= 1u << ad;
@@ -114,7 +125,7 @@ __host__ __device__ __forceinline__ T point_rhs(const Dims &d, const Coef<T> &cf
 #pragma unroll
     for (int dd = 0; dd < 2 * DIM; ++dd) {
         const int cc = (dd >> 1) == 0 ? ci : ((dd >> 1) == 1 ? cj : cl);
-        const T term = coef_arr<T>(cf, dd)[cc] * ub[idx + dir_off(d, dd)];
+        const T term = coef_arr<T>(cf, dd)[cc] * ub[nb[dd]];
         r -= ((inb >> dd) & 1u) ? T(0) : term;
     }
     return r;
@@ -126,10 +137,12 @@ __host__ __device__ __forceinline__ long long axis_stride(const Dims &d, int a)
     return (a == 0) ? 1LL : ((a == 1) ? d.st[1] : d.st[2]);
 }
 
-// node index of point k of a chunk
+// slot of point k of a chunk
 __host__ __device__ __forceinline__ long long point_index(const Dims &d, const Chunk &ch, int k)
 {
     const int ax = ch.axdir >> 1, sg = (ch.axdir & 1) ? 1 : -1;
+    if (d.layout != LAYOUT_ROW)
+        return nidx(d, ch.c0[0] + (ax == 0 ? sg * k : 0), ch.c0[1] + (ax == 1 ? sg * k : 0), 0);
     return (long long)ch.c0[0] + (long long)ch.c0[1] * d.st[1] + (long long)ch.c0[2] * d.st[2] +
            (long long)(sg * k) * axis_stride(d, ax);
 }
@@ -141,7 +154,11 @@ __host__ __device__ __forceinline__ long long point_index(const Dims &d, const C
 // rr(k) returns the right-hand side of point k (point_rhs) for k < CH - 1; it
 // is called once per k, in increasing order, so it may compute the value on
 // the spot.  rL is the right-hand side of the last point (index len - 1).
-template <typename T, int DIM, bool MATRIX, bool DATA, typename RR>
+// DIAG_FROM_OFF: the axis part of the diagonal is taken as -(a + c) instead of
+// being loaded; valid for the FP64 forward operator, whose stored diagonal
+// arrays are exactly -(lo + hi) (the same rounding), and it saves a third of
+// the lane's coefficient loads.
+template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF = false, typename RR>
 __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
                                                       const Chunk &ch, int t, const RedArrays<T> &s,
                                                       LaneState<T> &st)
@@ -152,20 +169,13 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     const uint8_t fl = ch.flags;
     const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
-    const long long step = sg * axis_stride(d, ax);
-    const long long p0 = c0x + c0y * d.st[1] + (DIM == 3 ? c0z * d.st[2] : 0);
     const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
     const T *Pback = coef_arr_rt<T, DIM>(cf, ad ^ 1);
     const T *Pfwd = coef_arr_rt<T, DIM>(cf, ad);
     const int ex = (ax == 0) ? sg : 0, ey = (ax == 1) ? sg : 0, ez = (ax == 2) ? sg : 0;
     st.L = L;
-    st.sg = sg;
     st.prev = ch.prev;
     st.hp = hp;
-    st.p0 = p0;
-    st.step = step;
-    st.cax = cax;
-    st.Pfwd = Pfwd;
 
     // coefficients along the chunk, all loaded before the elimination chain so
     // that their latency is paid once: a (toward the predecessor point), c
@@ -181,7 +191,7 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
         const int ca = (k < L) ? cax + k * sg : cax; // clamped: stays inside the arrays
         Av[k] = Pback[ca];
         Cv[k] = Pfwd[ca];
-        Bv[k] = Pdg[ca];
+        Bv[k] = DIAG_FROM_OFF ? -(Av[k] + Cv[k]) : Pdg[ca];
     }
     // the last point's row (the node): a, b, its right-hand side, and its
     // coupling to the successor

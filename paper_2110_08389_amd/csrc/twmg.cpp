@@ -679,7 +679,7 @@ struct Level {
     long long cs = 0;                 // entries per coefficient array
     std::vector<double> hblk[2];      // host coefficient blocks [forward, transposed] (layout of Coef)
     Coef<double> hc64[2];
-    double *u = nullptr, *f = nullptr;   // FP64 work arrays (levels >= 1)
+    double *u = nullptr, *f = nullptr;   // FP64 work arrays (levels >= 1, and level 0 when its layout is split)
     float *u32 = nullptr, *f32 = nullptr; // FP32 work arrays (all levels)
 };
 
@@ -730,18 +730,18 @@ size_t workspace_layout(mg_handle *h, bool assign)
     };
     for (int l = 0; l < h->nlev; ++l) {
         Level &L = h->lev[l];
-        const size_t n = (size_t)L.d.nn * B;
+        const size_t n = (size_t)L.d.bs * B;
+        // level 0 works in the caller's arrays unless its layout is split
+        const bool own = l > 0 || L.d.layout != LAYOUT_ROW;
         size_t ou = 0, of = 0;
-        if (l > 0) {
+        if (own) {
             ou = take(n * sizeof(double));
             of = take(n * sizeof(double));
         }
         const size_t ou32 = take(n * sizeof(float)), of32 = take(n * sizeof(float));
         if (assign) {
-            if (l > 0) {
-                L.u = (double *)(h->ws + ou);
-                L.f = (double *)(h->ws + of);
-            }
+            L.u = own ? (double *)(h->ws + ou) : nullptr;
+            L.f = own ? (double *)(h->ws + of) : nullptr;
             L.u32 = (float *)(h->ws + ou32);
             L.f32 = (float *)(h->ws + of32);
         }
@@ -754,8 +754,8 @@ int clear_workspace(mg_handle *h)
     // coarse arrays start at zero: their boundary entries are never written
     for (int l = 0; l < h->nlev; ++l) {
         Level &L = h->lev[l];
-        const long long n = L.d.nn * h->grid.batch;
-        if (l > 0) {
+        const long long n = L.d.bs * h->grid.batch;
+        if (L.u) {
             HIPCHK(launch_fill<double>(L.u, n, 0.0, h->stream));
             HIPCHK(launch_fill<double>(L.f, n, 0.0, h->stream));
         }
@@ -971,7 +971,7 @@ int build_tail(mg_handle *h)
     const int nl = h->nlev;
     int lt = -1;
     for (int l = nl - 2; l >= 0; --l) {
-        bool fits = true;
+        bool fits = h->lev[l].d.layout == LAYOUT_ROW;
         for (int sl = 0; sl < 2; ++sl)
             for (int c = 0; c < 2; ++c) fits = fits && h->lev[l].tab[sl][c].nwg_big == 0;
         std::vector<unsigned char> img;
@@ -1023,6 +1023,16 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     // axis has an odd number of cells or only two
     int cur[3] = {grid->n[0], grid->n[1], dim == 3 ? grid->n[2] : 0};
     int nl = 0;
+    int orient = LAYOUT_ROW;
+    {
+        const char *env = std::getenv("TWMG_ROW_LAYOUT");
+        const bool row_only = env && env[0] == '1';
+        if (dim == 2 && !row_only) {
+            if (opt->smoother == MG_TWEED) orient = LAYOUT_TWEED;
+            else if (opt->smoother == MG_WIREFRAME) orient = LAYOUT_WIREFRAME;
+            else if (opt->smoother == MG_ZEBRA_Y) orient = LAYOUT_COLUMNS;
+        }
+    }
     while (true) {
         Level &L = h->lev[nl];
         L.d.dim = dim;
@@ -1036,6 +1046,11 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         L.d.st[1] = L.g.np[0];
         L.d.st[2] = dim == 3 ? (long long)L.g.np[0] * L.g.np[1] : 0;
         L.d.nn = (long long)L.g.np[0] * L.g.np[1] * L.g.np[2];
+        // split layout for the large 2D levels of line smoothers (lines along y
+        // contiguous); small levels stay row-major (the coarse-level kernel
+        // keeps them in LDS in that layout)
+        L.d.layout = (L.d.nn >= SPLIT_MIN_NODES) ? orient : LAYOUT_ROW;
+        L.d.bs = L.d.layout == LAYOUT_ROW ? L.d.nn : 2 * L.d.nn;
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
         for (int a = 0; a < dim; ++a) {
@@ -1277,7 +1292,7 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
                 // r = f - A u (FP64) rounded to FP32; e = FP32 cycle on A e = r from 0; u += e
                 HIPCHK(launch_resnorm_to_f32(L.d, L.c64[adj], u, f, L.f32, h->partial, NORM_PARTS, h->normv, B,
                                              h->stream));
-                HIPCHK(launch_fill<float>(L.u32, L.d.nn * B, 0.0f, h->stream));
+                HIPCHK(launch_fill<float>(L.u32, L.d.bs * B, 0.0f, h->stream));
                 if ((rc = cycle<float>(h, 0, L.u32, L.f32, adj))) return rc;
                 HIPCHK(launch_ir_update(L.d, u, L.u32, B, h->stream));
             } else {
@@ -1309,6 +1324,18 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
 }
 
 bool bad_level(const mg_handle *h, int lv) { return !h || lv < 0 || lv >= h->nlev; }
+
+// does level L keep its own arrays in a split layout?
+bool split(const Level &L) { return L.d.layout != LAYOUT_ROW; }
+
+// the caller's row-major view of a level
+Dims row_dims(const Dims &d)
+{
+    Dims r = d;
+    r.layout = LAYOUT_ROW;
+    r.bs = r.nn;
+    return r;
+}
 
 } // namespace
 
@@ -1422,31 +1449,54 @@ int mg_vcycle(mg_handle *h, double *u, const double *f)
     if (!h || !u || !f) return MG_EINVAL;
     int rc = ensure_workspace(h);
     if (rc) return rc;
-    return cycle<double>(h, 0, u, f, 0);
+    Level &L = h->lev[0];
+    if (!split(L)) return cycle<double>(h, 0, u, f, 0);
+    const int B = h->grid.batch;
+    HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+    HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
+    if ((rc = cycle<double>(h, 0, L.u, L.f, 0))) return rc;
+    HIPCHK(launch_convert<double>(L.d, L.u, u, 0, B, h->stream));
+    return MG_OK;
 }
 
 int mg_solve(mg_handle *h, double *u, const double *f, const double *bc, double tol, mg_stats *stats)
 {
     if (!h || !u || !f || !(tol >= 0)) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
     Level &L = h->lev[0];
+    const int B = h->grid.batch;
     const bool zero = !(h->opt.flags & MG_INITIAL_GUESS);
-    if (bc || zero) HIPCHK(launch_set_boundary(L.d, u, bc, zero ? 1 : 0, h->grid.batch, h->stream));
-    return solve_impl(h, u, f, tol, stats, 0);
+    if (bc || zero) HIPCHK(launch_set_boundary(row_dims(L.d), u, bc, zero ? 1 : 0, B, h->stream));
+    if (!split(L)) return solve_impl(h, u, f, tol, stats, 0);
+    HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+    HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
+    rc = solve_impl(h, L.u, L.f, tol, stats, 0);
+    HIPCHK(launch_convert<double>(L.d, L.u, u, 0, B, h->stream));
+    return rc;
 }
 
 int mg_solve_adjoint(mg_handle *h, double *lam, const double *w, double tol, mg_stats *stats)
 {
     if (!h || !lam || !w || !(tol >= 0)) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
     Level &L = h->lev[0];
-    HIPCHK(launch_fill<double>(lam, L.d.nn * h->grid.batch, 0.0, h->stream));
-    return solve_impl(h, lam, w, tol, stats, 1);
+    const int B = h->grid.batch;
+    HIPCHK(launch_fill<double>(lam, L.d.nn * B, 0.0, h->stream));
+    if (!split(L)) return solve_impl(h, lam, w, tol, stats, 1);
+    HIPCHK(launch_fill<double>(L.u, L.d.bs * B, 0.0, h->stream));
+    HIPCHK(launch_convert<double>(L.d, w, L.f, 1, B, h->stream));
+    rc = solve_impl(h, L.u, L.f, tol, stats, 1);
+    HIPCHK(launch_convert<double>(L.d, L.u, lam, 0, B, h->stream));
+    return rc;
 }
 
 int mg_bc_grad(mg_handle *h, const double *lam, const double *w, double *grad_bc)
 {
     if (!h || !lam || !w || !grad_bc) return MG_EINVAL;
     Level &L = h->lev[0];
-    HIPCHK(launch_bc_grad(L.d, L.c64[0], lam, w, grad_bc, h->grid.batch, h->stream));
+    HIPCHK(launch_bc_grad(row_dims(L.d), L.c64[0], lam, w, grad_bc, h->grid.batch, h->stream));
     return MG_OK;
 }
 
@@ -1454,52 +1504,151 @@ int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out
 {
     if (!h || !u || !f || !out_inf) return MG_EINVAL;
     Level &L = h->lev[0];
-    HIPCHK(launch_resnorm<double>(L.d, L.c64[0], u, f, h->partial, NORM_PARTS, h->normv, h->grid.batch, h->stream));
+    HIPCHK(launch_resnorm<double>(row_dims(L.d), L.c64[0], u, f, h->partial, NORM_PARTS, h->normv, h->grid.batch,
+                                  h->stream));
     return read_norm(h, out_inf);
 }
 
 int mg_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)
 {
     if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
-    for (int s = 0; s < nu; ++s) {
-        const int rc = relax<double>(h, lv, u, f, adjoint ? 1 : 0);
-        if (rc) return rc;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
+    Level &L = h->lev[lv];
+    const int B = h->grid.batch;
+    double *uu = u;
+    const double *ff = f;
+    if (split(L)) {
+        HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+        HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
+        uu = L.u;
+        ff = L.f;
     }
+    for (int s = 0; s < nu; ++s)
+        if ((rc = relax<double>(h, lv, uu, ff, adjoint ? 1 : 0))) return rc;
+    if (split(L)) HIPCHK(launch_convert<double>(L.d, L.u, u, 0, B, h->stream));
     return MG_OK;
 }
 
 int mg_smooth_f32(mg_handle *h, int lv, float *u, const float *f, int nu, int adjoint)
 {
     if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
-    for (int s = 0; s < nu; ++s) {
-        const int rc = relax<float>(h, lv, u, f, adjoint ? 1 : 0);
-        if (rc) return rc;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
+    Level &L = h->lev[lv];
+    const int B = h->grid.batch;
+    float *uu = u;
+    const float *ff = f;
+    if (split(L)) {
+        HIPCHK(launch_convert<float>(L.d, u, L.u32, 1, B, h->stream));
+        HIPCHK(launch_convert<float>(L.d, f, L.f32, 1, B, h->stream));
+        uu = L.u32;
+        ff = L.f32;
     }
+    for (int s = 0; s < nu; ++s)
+        if ((rc = relax<float>(h, lv, uu, ff, adjoint ? 1 : 0))) return rc;
+    if (split(L)) HIPCHK(launch_convert<float>(L.d, L.u32, u, 0, B, h->stream));
     return MG_OK;
 }
 
 int mg_residual(mg_handle *h, int lv, const double *u, const double *f, double *d, int adjoint)
 {
     if (bad_level(h, lv) || !u || !f || !d) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
     Level &L = h->lev[lv];
-    HIPCHK(launch_residual<double>(L.d, L.c64[adjoint ? 1 : 0], u, f, d, h->grid.batch, h->stream));
+    const int B = h->grid.batch;
+    if (!split(L)) {
+        HIPCHK(launch_residual<double>(L.d, L.d, L.c64[adjoint ? 1 : 0], u, f, d, B, h->stream));
+        return MG_OK;
+    }
+    HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+    HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
+    HIPCHK(launch_residual<double>(L.d, row_dims(L.d), L.c64[adjoint ? 1 : 0], L.u, L.f, d, B, h->stream));
     return MG_OK;
 }
 
 int mg_residual_restrict(mg_handle *h, int lv, const double *u, const double *f, double *fc, double *uc, int adjoint)
 {
     if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || !fc || !uc) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
     Level &L = h->lev[lv], &C = h->lev[lv + 1];
-    HIPCHK(launch_residual_restrict<double>(L.d, C.d, L.c64[adjoint ? 1 : 0], u, f, fc, uc, h->grid.batch,
-                                            h->stream));
+    const int B = h->grid.batch;
+    const double *uu = u, *ff = f;
+    double *fcc = fc, *ucc = uc;
+    if (split(L)) {
+        HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+        HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
+        uu = L.u;
+        ff = L.f;
+    }
+    if (split(C)) {
+        // the kernel writes interior nodes only: carry the caller's boundary entries through
+        HIPCHK(launch_convert<double>(C.d, fc, C.f, 1, B, h->stream));
+        HIPCHK(launch_convert<double>(C.d, uc, C.u, 1, B, h->stream));
+        fcc = C.f;
+        ucc = C.u;
+    }
+    HIPCHK(launch_residual_restrict<double>(L.d, C.d, L.c64[adjoint ? 1 : 0], uu, ff, fcc, ucc, B, h->stream));
+    if (split(C)) {
+        HIPCHK(launch_convert<double>(C.d, C.f, fc, 0, B, h->stream));
+        HIPCHK(launch_convert<double>(C.d, C.u, uc, 0, B, h->stream));
+    }
     return MG_OK;
 }
 
 int mg_prolong_add(mg_handle *h, int lv, const double *ec, double *u)
 {
     if (bad_level(h, lv) || lv == h->nlev - 1 || !ec || !u) return MG_EINVAL;
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
     Level &L = h->lev[lv], &C = h->lev[lv + 1];
-    HIPCHK(launch_prolong_add<double>(L.d, C.d, ec, u, h->grid.batch, h->stream));
+    const int B = h->grid.batch;
+    const double *ee = ec;
+    double *uu = u;
+    if (split(C)) {
+        HIPCHK(launch_convert<double>(C.d, ec, C.u, 1, B, h->stream));
+        ee = C.u;
+    }
+    if (split(L)) {
+        HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+        uu = L.u;
+    }
+    HIPCHK(launch_prolong_add<double>(L.d, C.d, ee, uu, B, h->stream));
+    if (split(L)) HIPCHK(launch_convert<double>(L.d, L.u, u, 0, B, h->stream));
+    return MG_OK;
+}
+
+int mg_level_array_len(const mg_handle *h, int lv, long long *len)
+{
+    if (bad_level(h, lv) || !len) return MG_EINVAL;
+    *len = h->lev[lv].d.bs;
+    return MG_OK;
+}
+
+int mg_to_layout(mg_handle *h, int lv, const double *src, double *dst)
+{
+    if (bad_level(h, lv) || !src || !dst) return MG_EINVAL;
+    HIPCHK(launch_convert<double>(h->lev[lv].d, src, dst, 1, h->grid.batch, h->stream));
+    return MG_OK;
+}
+
+int mg_from_layout(mg_handle *h, int lv, const double *src, double *dst)
+{
+    if (bad_level(h, lv) || !src || !dst) return MG_EINVAL;
+    HIPCHK(launch_convert<double>(h->lev[lv].d, src, dst, 0, h->grid.batch, h->stream));
+    return MG_OK;
+}
+
+int mg_half_sweep(mg_handle *h, int lv, double *u, const double *f, int slot, int colour, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || h->checker || slot < 0 || slot > 1 || colour < 0 ||
+        colour > 1 || h->slot_motif[slot] < 0)
+        return MG_EINVAL;
+    Level &L = h->lev[lv];
+    const int adj = adjoint ? 1 : 0;
+    HIPCHK(launch_block_sweep<double>(L.d, L.c64[adj], u, f, L.tab[slot][colour], adj, h->grid.batch, h->stream));
     return MG_OK;
 }
 
@@ -1561,10 +1710,46 @@ int mg_debug_setup_host(const mg_grid *grid, const mg_stretching *stretch, const
     return MG_OK;
 }
 
+static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint, const Dims &D);
+
 int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)
 {
     if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
     if (h->checker) return MG_EUNSUPPORTED;
+    return host_smooth(h, lv, u, f, nu, adjoint, row_dims(h->lev[lv].d));
+}
+
+int mg_debug_host_smooth_layout(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)
+{
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || nu < 0) return MG_EINVAL;
+    if (h->checker) return MG_EUNSUPPORTED;
+    const Dims &D = h->lev[lv].d;
+    const int B = h->grid.batch;
+    const int nz = D.dim == 3 ? D.n[2] : 0;
+    std::vector<double> us((size_t)D.bs * B, 0.0), fs((size_t)D.bs * B, 0.0);
+    for (int b = 0; b < B; ++b)
+        for (int l = 0; l <= nz; ++l)
+            for (int j = 0; j <= D.n[1]; ++j)
+                for (int i = 0; i <= D.n[0]; ++i) {
+                    const long long r = (long long)b * D.nn + i + j * D.st[1] + l * D.st[2];
+                    const long long q = (long long)b * D.bs + nidx(D, i, j, l);
+                    us[q] = u[r];
+                    fs[q] = f[r];
+                }
+    const int rc = host_smooth(h, lv, us.data(), fs.data(), nu, adjoint, D);
+    for (int b = 0; b < B; ++b)
+        for (int l = 0; l <= nz; ++l)
+            for (int j = 0; j <= D.n[1]; ++j)
+                for (int i = 0; i <= D.n[0]; ++i)
+                    u[(long long)b * D.nn + i + j * D.st[1] + l * D.st[2]] = us[(long long)b * D.bs + nidx(D, i, j, l)];
+    return rc;
+}
+
+} // extern "C"
+
+// the kernel's per-lane steps run sequentially on the host, on arrays of layout D
+static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint, const Dims &D)
+{
     Level &L = h->lev[lv];
     const int adj = adjoint ? 1 : 0;
     const Coef<double> &c = L.hc64[adj];
@@ -1581,16 +1766,16 @@ int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int n
                 const int colour = adj ? 1 - q : q;
                 const HostTable &t = L.htab[s][colour];
                 for (int b = 0; b < h->grid.batch; ++b) {
-                    double *ub = u + (long long)b * L.d.nn;
-                    const double *fb = f + (long long)b * L.d.nn;
+                    double *ub = u + (long long)b * D.bs;
+                    const double *fb = f + (long long)b * D.bs;
                     const std::vector<NodeFac<double>> &fac = L.hfac[s][colour][adj];
                     for (const WGDesc &w : t.wgs) {
                         std::fill(red.begin(), red.end(), 0.0);
                         const Chunk *chs = &t.chunks[w.chunk0];
                         for (int ln = 0; ln < w.nchunk; ++ln)
                             for (int k = 0; k < chs[ln].len; ++k)
-                                pt[ln * CH + k] = (L.d.dim == 2) ? point_rhs<double, 2>(L.d, c, ub, fb, chs[ln], k)
-                                                                 : point_rhs<double, 3>(L.d, c, ub, fb, chs[ln], k);
+                                pt[ln * CH + k] = (D.dim == 2) ? point_rhs<double, 2>(D, c, ub, fb, chs[ln], k)
+                                                               : point_rhs<double, 3>(D, c, ub, fb, chs[ln], k);
                         for (int ln = 0; ln < w.nchunk; ++ln) {
                             if (L.d.dim == 2)
                                 sweep_phase1<double, 2, false, true>(L.d, c, [&](int k) { return pt[ln * CH + k]; }, pt[ln * CH + chs[ln].len - 1],
@@ -1604,13 +1789,11 @@ int mg_debug_host_smooth(mg_handle *h, int lv, double *u, const double *f, int n
                                                   dl.data(), r.x);
                         for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(&pt[ln * CH], ln, r, st[ln]);
                         for (int ln = 0; ln < w.nchunk; ++ln)
-                            for (int k = 0; k < chs[ln].len; ++k) ub[point_index(L.d, chs[ln], k)] = pt[ln * CH + k];
+                            for (int k = 0; k < chs[ln].len; ++k) ub[point_index(D, chs[ln], k)] = pt[ln * CH + k];
                     }
                 }
             }
         }
     return MG_OK;
 }
-
-} // extern "C"
 

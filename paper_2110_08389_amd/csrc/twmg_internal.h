@@ -84,12 +84,41 @@ struct WGDesc {
     int nblock;   // <= NT
 };
 
+// Node array layouts.  LAYOUT_ROW: row-major, x fastest (the caller's layout).
+// The split layouts (2D only) keep two planes of nn slots each: plane R,
+// row-major, holds the points whose block lines run along x; plane C, column-
+// major (y fastest), holds those whose lines run along y.  Every line of a
+// block is then contiguous in memory.  With i' = min(i, nx-i), j' = min(j, ny-j):
+//   LAYOUT_TWEED     : plane C iff i' > j'  (tweed legs along y)
+//   LAYOUT_WIREFRAME : plane C iff i' < j'  (wireframe sides along y)
+//   LAYOUT_COLUMNS   : plane C for every node (lines along y everywhere)
+enum Layout : int { LAYOUT_ROW = 0, LAYOUT_TWEED = 1, LAYOUT_WIREFRAME = 2, LAYOUT_COLUMNS = 3 };
+
+// levels with at least this many nodes use the split layout of their smoother
+constexpr long long SPLIT_MIN_NODES = 129 * 129;
+
 struct Dims {
     int dim;
     int n[3];          // cells per axis (0 beyond dim)
-    long long st[3];   // node strides: 1, nx+1, (nx+1)(ny+1)
+    long long st[3];   // row-major node strides: 1, nx+1, (nx+1)(ny+1)
     long long nn;      // nodes per problem
+    int layout;        // Layout
+    long long bs;      // array length per problem (batch stride): nn, or 2 nn when split
 };
+
+// split layouts: is node (i, j) stored in plane C?
+__host__ __device__ inline bool col_plane(const Dims &d, int i, int j)
+{
+    const int ip = i < d.n[0] - i ? i : d.n[0] - i, jp = j < d.n[1] - j ? j : d.n[1] - j;
+    return d.layout == LAYOUT_TWEED ? ip > jp : (d.layout == LAYOUT_WIREFRAME ? ip < jp : true);
+}
+
+// slot of node (i, j, l) in an array of layout d.layout
+__host__ __device__ inline long long nidx(const Dims &d, int i, int j, int l)
+{
+    if (d.layout == LAYOUT_ROW) return i + j * d.st[1] + l * d.st[2];
+    return col_plane(d, i, j) ? d.nn + j + (long long)i * (d.n[1] + 1) : i + j * d.st[1];
+}
 
 // Coefficients of one level (one direction of the operator), stored as nine
 // arrays of cs entries in one block: lo_x, hi_x, lo_y, hi_y, lo_z, hi_z, dg_x,
@@ -176,7 +205,11 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
 template <typename T>
 hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s);
 template <typename T>
-hipError_t launch_residual(const Dims &d, const Coef<T> &c, const T *u, const T *f, T *r, int batch, hipStream_t s);
+hipError_t launch_residual(const Dims &d, const Dims &dout, const Coef<T> &c, const T *u, const T *f, T *r, int batch,
+                           hipStream_t s);
+// row-major <-> layout d.layout (a plain copy for LAYOUT_ROW)
+template <typename T>
+hipError_t launch_convert(const Dims &d, const T *src, T *dst, int to_split, int batch, hipStream_t s);
 template <typename T>
 hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
                                     T *uc, int batch, hipStream_t s);

@@ -119,6 +119,28 @@ def test_kernel_steps_on_host_match_oracle(n, kind, c, sm):
     pkg.capi().mg_destroy(h)
 
 
+@pytest.mark.parametrize("n,kind,c,sm", [([256, 256], "tanh_wall", 3.0, "tweed"), ([256, 128], "tanh_wall", 2.5, "tweed"),
+                                        ([256, 256], "sinh_centre", 4.0, "wireframe"),
+                                        ([128, 256], "sinh_centre", 3.0, "wireframe"),
+                                        ([256, 192], "tanh_wall", 2.0, "zebra_y"), ([256, 256], "tanh_wall", 2.0, "adz")])
+def test_kernel_steps_in_device_layout_match_oracle(n, kind, c, sm):
+    """The same per-lane steps addressing the level's device layout (lines
+    along y stored column-major on the large levels) equal the oracle's sweep."""
+    rc, h = host_handle(n, kind, c, sm)
+    assert rc == 0
+    xs = [O.coords(kind, c, k) for k in n]
+    shape = O.Hierarchy(xs, sm, maxlev=1).shape(0)
+    u = inputs.normal(shape, 3)
+    f = inputs.normal(shape, 4)
+    for adj in (0, 1):
+        Ho = O.Hierarchy(xs, sm, transpose=bool(adj), maxlev=1)
+        ue = u.copy()
+        assert pkg.capi().mg_debug_host_smooth_layout(h, 0, ue.ctypes.data_as(C.c_void_p),
+                                                      f.ctypes.data_as(C.c_void_p), 1, adj) == 0
+        assert rel_inf(ue, Ho.smooth(u, f, 1)) < 1e-12
+    pkg.capi().mg_destroy(h)
+
+
 @pytest.mark.parametrize("n,kind,c,sm,maxchunks", [([4096, 4096], "tanh_wall", 3.0, "tweed", 512),
                                                     ([2048, 2048], "sinh_centre", 4.0, "wireframe", 512),
                                                     ([256, 256, 256], "tanh_wall", 2.5, "tweed", 512),
