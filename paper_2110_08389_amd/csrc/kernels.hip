@@ -487,13 +487,124 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coe
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D tiles: the stencil kernels of the transfer operators and the norm stage a
+// node rectangle of u in LDS once (instead of five neighbour loads per node),
+// in the thread order of the plane that holds the rectangle, so that the loads
+// are contiguous in either layout.
+// ---------------------------------------------------------------------------
+// does plane C (column-major) hold node (i, j)?  (false for LAYOUT_ROW)
+__device__ __forceinline__ bool in_col(const Dims &d, int i, int j)
+{
+    return d.layout != LAYOUT_ROW && col_plane(d, i, j);
+}
+
+// rectangle [ia, ia + W) x [ja, ja + H) of a (layout d) -> t[y * P + x];
+// nodes outside the grid read as 0.  jfast: thread order with j fastest.
+template <typename T, int W, int H, int P>
+__device__ __forceinline__ void load_rect(const Dims &d, const T *__restrict__ a, int ia, int ja, bool jfast, T *t)
+{
+    for (int q = threadIdx.x; q < W * H; q += blockDim.x) {
+        const int x = jfast ? q / H : q % W, y = jfast ? q % H : q / W;
+        const int i = ia + x, j = ja + y;
+        T v = 0;
+        if (i >= 0 && i <= d.n[0] && j >= 0 && j <= d.n[1]) v = a[nidx(d, i, j, 0)];
+        t[y * P + x] = v;
+    }
+}
+
+// fused defect + full weighting, 16 x 16 coarse interior nodes per workgroup:
+// u on the 35 x 35 fine rectangle around them and the defect on the inner
+// 33 x 33 are staged in LDS, each fine defect computed once
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_tile(Dims fd, Dims cd, Coef<T> cf, const T *__restrict__ u,
+                                                       const T *__restrict__ f, T *__restrict__ fc,
+                                                       T *__restrict__ uc)
+{
+    constexpr int CT = 16, FW = 2 * CT + 1, UW = FW + 2;
+    __shared__ T su[UW * UW];
+    __shared__ T sd[FW * FW];
+    const int I0 = 1 + blockIdx.x * CT, J0 = 1 + blockIdx.y * CT;
+    const int fi = 2 * I0 - 1, fj = 2 * J0 - 1; // first fine node of the defect rectangle
+    const T *ub = u + (long long)blockIdx.z * fd.bs;
+    const T *fb = f + (long long)blockIdx.z * fd.bs;
+    const bool jf = in_col(fd, fi + CT, fj + CT);
+    load_rect<T, UW, UW, UW>(fd, ub, fi - 1, fj - 1, jf, su);
+    load_rect<T, FW, FW, FW>(fd, fb, fi, fj, jf, sd);
+    __syncthreads();
+    for (int q = threadIdx.x; q < FW * FW; q += blockDim.x) {
+        const int x = jf ? q / FW : q % FW, y = jf ? q % FW : q / FW;
+        const int i = fi + x, j = fj + y;
+        T r = 0;
+        if (i > 0 && i < fd.n[0] && j > 0 && j < fd.n[1]) {
+            const T *c = &su[(y + 1) * UW + (x + 1)];
+            T sum = cf.lo[0][i] * c[-1] + cf.hi[0][i] * c[1];
+            sum += cf.lo[1][j] * c[-UW] + cf.hi[1][j] * c[UW];
+            const T dg = cf.dg[0][i] + cf.dg[1][j];
+            r = sd[y * FW + x] - (sum + dg * c[0]);
+        }
+        sd[y * FW + x] = r;
+    }
+    __syncthreads();
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    const long long cb = (long long)blockIdx.z * cd.bs;
+    for (int q = threadIdx.x; q < CT * CT; q += blockDim.x) {
+        const int a = jf ? q / CT : q % CT, b = jf ? q % CT : q / CT;
+        const int I = I0 + a, J = J0 + b;
+        if (I >= cd.n[0] || J >= cd.n[1]) continue;
+        const T *c = &sd[(2 * b + 1) * FW + (2 * a + 1)];
+        T acc = 0;
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb) {
+            T rowacc = 0;
+#pragma unroll
+            for (int aa = -1; aa <= 1; ++aa) rowacc += w3[aa + 1] * c[bb * FW + aa];
+            acc += w3[bb + 1] * rowacc;
+        }
+        const long long p = cb + nidx(cd, I, J, 0);
+        fc[p] = acc;
+        uc[p] = T(0);
+    }
+}
+
+// bilinear prolongation + update, 32 x 32 fine nodes per workgroup; the coarse
+// 17 x 17 rectangle under them is staged in LDS
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_tile(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
+{
+    constexpr int FT = 32, CW = FT / 2 + 1;
+    __shared__ T se[CW * CW];
+    const int i0 = blockIdx.x * FT, j0 = blockIdx.y * FT;
+    T *ub = u + (long long)blockIdx.z * fd.bs;
+    const T *eb = ec + (long long)blockIdx.z * cd.bs;
+    const bool jf = in_col(fd, i0 + FT / 2, j0 + FT / 2);
+    load_rect<T, CW, CW, CW>(cd, eb, i0 / 2, j0 / 2, jf, se);
+    __syncthreads();
+    for (int q = threadIdx.x; q < FT * FT; q += blockDim.x) {
+        const int x = jf ? q / FT : q % FT, y = jf ? q % FT : q / FT;
+        const int i = i0 + x, j = j0 + y;
+        if (i <= 0 || i >= fd.n[0] || j <= 0 || j >= fd.n[1]) continue;
+        // coarse neighbours in the rectangle: (I - i0/2, J - j0/2)
+        const int X0 = (i >> 1) - i0 / 2, X1 = ((i + 1) >> 1) - i0 / 2;
+        const int Y0 = (j >> 1) - j0 / 2, Y1 = ((j + 1) >> 1) - j0 / 2;
+        const T r0 = (X0 == X1) ? se[Y0 * CW + X0] : T(0.5) * (se[Y0 * CW + X0] + se[Y0 * CW + X1]);
+        const T r1 = (X0 == X1) ? se[Y1 * CW + X0] : T(0.5) * (se[Y1 * CW + X0] + se[Y1 * CW + X1]);
+        const T v = (Y0 == Y1) ? r0 : T(0.5) * (r0 + r1);
+        ub[nidx(fd, i, j, 0)] += v;
+    }
+}
+
 template <typename T>
 hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
                                     T *uc, int batch, hipStream_t s)
 {
+    if (fd.dim == 2) {
+        dim3 tiles((cd.n[0] - 1 + 15) / 16, (cd.n[1] - 1 + 15) / 16, batch);
+        hipLaunchKernelGGL((k_restrict_tile<T>), tiles, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+        return hipGetLastError();
+    }
     dim3 grid(row_grid(cd), batch);
-    if (fd.dim == 2) hipLaunchKernelGGL((k_residual_restrict<T, 2>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
-    else hipLaunchKernelGGL((k_residual_restrict<T, 3>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+    hipLaunchKernelGGL((k_residual_restrict<T, 3>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
     return hipGetLastError();
 }
 
@@ -541,9 +652,13 @@ __global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *
 template <typename T>
 hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s)
 {
+    if (fd.dim == 2) {
+        dim3 tiles((fd.n[0] + 1 + 31) / 32, (fd.n[1] + 1 + 31) / 32, batch);
+        hipLaunchKernelGGL((k_prolong_tile<T>), tiles, dim3(256), 0, s, fd, cd, ec, u);
+        return hipGetLastError();
+    }
     dim3 grid(row_grid(fd), batch);
-    if (fd.dim == 2) hipLaunchKernelGGL((k_prolong_add<T, 2>), grid, dim3(256), 0, s, fd, cd, ec, u);
-    else hipLaunchKernelGGL((k_prolong_add<T, 3>), grid, dim3(256), 0, s, fd, cd, ec, u);
+    hipLaunchKernelGGL((k_prolong_add<T, 3>), grid, dim3(256), 0, s, fd, cd, ec, u);
     return hipGetLastError();
 }
 
@@ -790,6 +905,49 @@ __global__ void __launch_bounds__(256) k_resnorm(Dims d, Coef<T> cf, const T *__
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
 }
 
+// 2D tiled version: 32 x 32 nodes per tile, u staged with a one-node halo;
+// the workgroups stride over the tiles of their problem
+template <typename T, bool TO32>
+__global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const T *__restrict__ u,
+                                                      const T *__restrict__ f, float *__restrict__ r32,
+                                                      double *__restrict__ partial)
+{
+    constexpr int TS = 32, UW = TS + 2;
+    __shared__ T su[UW * UW];
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int tx = (d.n[0] + TS) / TS, ty = (d.n[1] + TS) / TS;
+    double m = 0.0;
+    bool nan = false;
+    for (int tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {
+        const int i0 = (tile % tx) * TS, j0 = (tile / tx) * TS;
+        const bool jf = in_col(d, i0 + TS / 2, j0 + TS / 2);
+        __syncthreads();
+        load_rect<T, UW, UW, UW>(d, u + boff, i0 - 1, j0 - 1, jf, su);
+        __syncthreads();
+        for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+            const int x = jf ? q / TS : q % TS, y = jf ? q % TS : q / TS;
+            const int i = i0 + x, j = j0 + y;
+            if (i > d.n[0] || j > d.n[1]) continue;
+            const long long p = boff + nidx(d, i, j, 0);
+            T r = 0;
+            if (i > 0 && i < d.n[0] && j > 0 && j < d.n[1]) {
+                const T *c = &su[(y + 1) * UW + (x + 1)];
+                T sum = cf.lo[0][i] * c[-1] + cf.hi[0][i] * c[1];
+                sum += cf.lo[1][j] * c[-UW] + cf.hi[1][j] * c[UW];
+                const T dg = cf.dg[0][i] + cf.dg[1][j];
+                r = f[p] - (sum + dg * c[0]);
+            }
+            if (TO32) r32[p] = (float)r;
+            const double a = fabs((double)r);
+            nan = nan || (a != a);
+            m = fmax(m, a);
+        }
+    }
+    if (nan) m = __builtin_inf();
+    m = block_max(m);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
+}
+
 __global__ void __launch_bounds__(256) k_max_final(const double *__restrict__ partial, int n, double *__restrict__ out)
 {
     double m = 0.0;
@@ -806,9 +964,13 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
     if (gx < 1) return hipErrorInvalidValue;
     const int rows = lrow_grid(d);
     if (gx > rows) gx = rows;
-    dim3 grid(gx, batch);
-    if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<T, 2, false>), grid, dim3(256), 0, s, d, c, u, f, nullptr, partial);
-    else hipLaunchKernelGGL((k_resnorm<T, 3, false>), grid, dim3(256), 0, s, d, c, u, f, nullptr, partial);
+    if (d.dim == 2) {
+        const int nt = ((d.n[0] + 32) / 32) * ((d.n[1] + 32) / 32);
+        if (gx > nt) gx = nt;
+        hipLaunchKernelGGL((k_resnorm_tile<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
+    } else {
+        hipLaunchKernelGGL((k_resnorm<T, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
+    }
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
     return hipGetLastError();
 }
@@ -820,9 +982,14 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
     if (gx < 1) return hipErrorInvalidValue;
     const int rows = lrow_grid(d);
     if (gx > rows) gx = rows;
-    dim3 grid(gx, batch);
-    if (d.dim == 2) hipLaunchKernelGGL((k_resnorm<double, 2, true>), grid, dim3(256), 0, s, d, c, u, f, r32, partial);
-    else hipLaunchKernelGGL((k_resnorm<double, 3, true>), grid, dim3(256), 0, s, d, c, u, f, r32, partial);
+    if (d.dim == 2) {
+        const int nt = ((d.n[0] + 32) / 32) * ((d.n[1] + 32) / 32);
+        if (gx > nt) gx = nt;
+        hipLaunchKernelGGL((k_resnorm_tile<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32,
+                           partial);
+    } else {
+        hipLaunchKernelGGL((k_resnorm<double, 3, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
+    }
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
     return hipGetLastError();
 }
