@@ -281,7 +281,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
                 const int P = t + (m0 + m) * NT, c = P / CH, k = P % CH;
                 const Chunk ch = s_ch[c < w.nchunk ? c : 0];
                 const bool valid = c < w.nchunk && k < ch.len;
-                rv[m] = point_rhs<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
+                rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
                 dst[m] = valid ? c * PS + k : NT * PS;
             }
 #pragma unroll
@@ -298,9 +298,13 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         nfl = ch.nflags;
         ext = ch.ext;
         nf = fac[w.chunk0 + t];
+        T tb, tf;
+        chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
         const T *rp = &s_pt[t * PS];
-        sweep_phase1<T, DIM, false, true, DOFF>(d, cf, [&](int k) { return rp[k]; }, rp[ch.len - 1], ch, t, red,
-                                                st);
+        const int L = ch.len;
+        const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
+        sweep_phase1<T, DIM, false, true, DOFF>(
+            d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, ch, t, red, st);
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
@@ -748,9 +752,16 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         ext = ch.ext;
         nf = fac[w.chunk0 + t];
         const int L = ch.len;
-        const T rL = point_rhs<T, DIM>(d, cf, ub, fb, ch, L - 1);
+        T tb, tf;
+        chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
+        const T rL = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, L - 1) - tf - (L == 1 ? tb : T(0));
         sweep_phase1<T, DIM, false, true>(
-            d, cf, [&](int k) { return point_rhs<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0); }, rL, ch, t, red, st);
+            d, cf,
+            [&](int k) {
+                const T r = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
+                return k == 0 ? r - tb : r;
+            },
+            rL, ch, t, red, st);
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);

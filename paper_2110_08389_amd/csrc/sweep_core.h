@@ -86,65 +86,146 @@ template <typename T> struct LaneState {
     bool hp;
 };
 
-// Right-hand side of point k of a chunk: f minus the couplings to every
-// neighbour outside the block (other colour, or boundary nodes).
-template <typename T, int DIM>
-__host__ __device__ __forceinline__ T point_rhs(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
-                                                const T *__restrict__ fb, const Chunk &ch, int k)
+// 32-bit slot of node (i, j, l) within one problem's array (every per-problem
+// array is far below 2^31 elements)
+__host__ __device__ __forceinline__ int slot32(const Dims &d, int i, int j, int l)
 {
-    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
-    const int sg = (ad & 1) ? 1 : -1;
-    const bool hp = ch.flags & CF_PREV, hn = ch.flags & CF_NEXT, jn = ch.flags & CF_JUNCTION;
-    const int ci = ch.c0[0] + (ax == 0 ? sg * k : 0), cj = ch.c0[1] + (ax == 1 ? sg * k : 0),
-              cl = (DIM == 3) ? ch.c0[2] + (ax == 2 ? sg * k : 0) : 0;
-    // slots of the point and of its 2*DIM neighbours (x-, x+, y-, y+, z-, z+)
-    long long nb[2 * DIM];
-    long long idx;
-    if (DIM == 2 && d.layout != LAYOUT_ROW) {
-        idx = nidx(d, ci, cj, 0);
-        nb[0] = nidx(d, ci - 1, cj, 0);
-        nb[1] = nidx(d, ci + 1, cj, 0);
-        nb[2] = nidx(d, ci, cj - 1, 0);
-        nb[3] = nidx(d, ci, cj + 1, 0);
-    } else {
-        idx = ci + cj * d.st[1] + (DIM == 3 ? cl * d.st[2] : 0);
-#pragma unroll
-        for (int dd = 0; dd < 2 * DIM; ++dd) nb[dd] = idx + dir_off(d, dd);
+    if (d.layout == LAYOUT_ROW) return i + j * (int)d.st[1] + l * (int)d.st[2];
+    return col_plane(d, i, j) ? (int)d.nn + j + i * (d.n[1] + 1) : i + j * (int)d.st[1];
+}
+
+// slots of node (i, j, l) and of its neighbours x-, x+, y-, y+ (, z-, z+).  In
+// a split layout a node's neighbours share its plane unless |i' - j'| <= 1,
+// so away from that band they are fixed offsets in the plane.
+template <int DIM> struct NbSlots {
+    int p, nb[2 * DIM];
+};
+template <int DIM> __host__ __device__ __forceinline__ NbSlots<DIM> nb_slots(const Dims &d, int i, int j, int l)
+{
+    NbSlots<DIM> s;
+    if (DIM == 3 || d.layout == LAYOUT_ROW) {
+        const int S1 = (int)d.st[1], S2 = (int)d.st[2];
+        s.p = i + j * S1 + (DIM == 3 ? l * S2 : 0);
+        s.nb[0] = s.p - 1;
+        s.nb[1] = s.p + 1;
+        s.nb[2] = s.p - S1;
+        s.nb[3] = s.p + S1;
+        if (DIM == 3) {
+            s.nb[4] = s.p - S2;
+            s.nb[5] = s.p + S2;
+        }
+        return s;
     }
+    const int ip = i < d.n[0] - i ? i : d.n[0] - i, jp = j < d.n[1] - j ? j : d.n[1] - j;
+    const int dl = ip - jp;
+    if (d.layout != LAYOUT_COLUMNS && dl > -2 && dl < 2) {
+        s.p = slot32(d, i, j, 0);
+        s.nb[0] = slot32(d, i - 1, j, 0);
+        s.nb[1] = slot32(d, i + 1, j, 0);
+        s.nb[2] = slot32(d, i, j - 1, 0);
+        s.nb[3] = slot32(d, i, j + 1, 0);
+        return s;
+    }
+    const bool col = d.layout == LAYOUT_TWEED ? dl > 0 : (d.layout == LAYOUT_WIREFRAME ? dl < 0 : true);
+    if (col) {
+        const int S = d.n[1] + 1;
+        s.p = (int)d.nn + j + i * S;
+        s.nb[0] = s.p - S;
+        s.nb[1] = s.p + S;
+        s.nb[2] = s.p - 1;
+        s.nb[3] = s.p + 1;
+    } else {
+        const int S = (int)d.st[1];
+        s.p = i + j * S;
+        s.nb[0] = s.p - 1;
+        s.nb[1] = s.p + 1;
+        s.nb[2] = s.p - S;
+        s.nb[3] = s.p + S;
+    }
+    return s;
+}
+
+// in-block directions of point k of a chunk (bit d set: the neighbour in
+// direction d belongs to the block)
+__host__ __device__ __forceinline__ unsigned inblock_dirs(const Chunk &ch, int k)
+{
+    const int L = ch.len, ad = ch.axdir;
     unsigned inb = 0;
-    if (k > 0 || hp) inb |= 1u << (ad ^ 1);
+    if (k > 0 || (ch.flags & CF_PREV)) inb |= 1u << (ad ^ 1);
     if (k < L - 1) inb |= 1u << ad;
     else {
-        if (hn) inb |= 1u << ch.nextdir;
-        if (jn) inb |= ch.jmask;
+        if (ch.flags & CF_NEXT) inb |= 1u << ch.nextdir;
+        if (ch.flags & CF_JUNCTION) inb |= ch.jmask;
     }
-    // every neighbour of an interior point exists, so all loads are issued
-    // unconditionally (no branches: the compiler can start them all at once)
-    // and in-block terms are dropped by a select
-    T r = fb[idx];
+    return inb;
+}
+
+// Right-hand side of point k of a chunk without its along-axis couplings: f
+// minus the couplings to the neighbours across the chunk axis that lie outside
+// the block.  Along the axis every neighbour is in the block except possibly
+// at the chunk's two ends (chunk_end_terms).
+template <typename T, int DIM>
+__host__ __device__ __forceinline__ T point_rhs_across(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                                       const T *__restrict__ fb, const Chunk &ch, int k)
+{
+    const int ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int ci = ch.c0[0] + (ax == 0 ? sg * k : 0), cj = ch.c0[1] + (ax == 1 ? sg * k : 0),
+              cl = (DIM == 3) ? ch.c0[2] + (ax == 2 ? sg * k : 0) : 0;
+    const NbSlots<DIM> s = nb_slots<DIM>(d, ci, cj, cl);
+    const unsigned inb = inblock_dirs(ch, k);
+    T r = fb[s.p];
 #pragma unroll
-    for (int dd = 0; dd < 2 * DIM; ++dd) {
-        const int cc = (dd >> 1) == 0 ? ci : ((dd >> 1) == 1 ? cj : cl);
-        const T term = coef_arr<T>(cf, dd)[cc] * ub[nb[dd]];
-        r -= ((inb >> dd) & 1u) ? T(0) : term;
+    for (int q = 0; q < DIM - 1; ++q) {
+        // q-th axis other than ax (chosen by selects: compile-time indices only)
+        const int a2 = (DIM == 2) ? 1 - ax : (q == 0 ? (ax == 0 ? 1 : 0) : (ax == 2 ? 1 : 2));
+        int sm = s.nb[0], sp = s.nb[1];
+        if (a2 == 1) {
+            sm = s.nb[2];
+            sp = s.nb[3];
+        }
+        if (DIM == 3 && a2 == 2) {
+            sm = s.nb[2 * DIM - 2];
+            sp = s.nb[2 * DIM - 1];
+        }
+        const int cc = a2 == 0 ? ci : (a2 == 1 ? cj : cl);
+        const T tm = cf.base[(2 * a2) * cf.cs + cc] * ub[sm];
+        const T tp = cf.base[(2 * a2 + 1) * cf.cs + cc] * ub[sp];
+        r -= ((inb >> (2 * a2)) & 1u) ? T(0) : tm;
+        r -= ((inb >> (2 * a2 + 1)) & 1u) ? T(0) : tp;
     }
     return r;
 }
 
-// node stride along axis a (selects: no indexed access to the argument struct)
-__host__ __device__ __forceinline__ long long axis_stride(const Dims &d, int a)
+// Along-axis couplings of a chunk's end points to neighbours outside the
+// block: tb for the first point's predecessor, tf for the last point's
+// successor (0 when in the block).
+template <typename T, int DIM>
+__host__ __device__ __forceinline__ void chunk_end_terms(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                                         const Chunk &ch, T &tb, T &tf)
 {
-    return (a == 0) ? 1LL : ((a == 1) ? d.st[1] : d.st[2]);
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int e[3] = {ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0};
+    const int i0 = ch.c0[0], j0 = ch.c0[1], l0 = DIM == 3 ? ch.c0[2] : 0;
+    const int iL = i0 + (L - 1) * e[0], jL = j0 + (L - 1) * e[1], lL = l0 + (L - 1) * e[2];
+    const int cax0 = ax == 0 ? i0 : (ax == 1 ? j0 : l0), caxL = cax0 + (L - 1) * sg;
+    const bool boff = !((inblock_dirs(ch, 0) >> (ad ^ 1)) & 1u);
+    const bool foff = !((inblock_dirs(ch, L - 1) >> ad) & 1u);
+    // the neighbours exist (the end points are interior); in-block ones are
+    // read too and dropped by the select
+    const T ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
+    const T ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
+    tb = boff ? coef_arr_rt<T, DIM>(cf, ad ^ 1)[cax0] * ubk : T(0);
+    tf = foff ? coef_arr_rt<T, DIM>(cf, ad)[caxL] * ufw : T(0);
 }
 
 // slot of point k of a chunk
-__host__ __device__ __forceinline__ long long point_index(const Dims &d, const Chunk &ch, int k)
+__host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &ch, int k)
 {
     const int ax = ch.axdir >> 1, sg = (ch.axdir & 1) ? 1 : -1;
-    if (d.layout != LAYOUT_ROW)
-        return nidx(d, ch.c0[0] + (ax == 0 ? sg * k : 0), ch.c0[1] + (ax == 1 ? sg * k : 0), 0);
-    return (long long)ch.c0[0] + (long long)ch.c0[1] * d.st[1] + (long long)ch.c0[2] * d.st[2] +
-           (long long)(sg * k) * axis_stride(d, ax);
+    return slot32(d, ch.c0[0] + (ax == 0 ? sg * k : 0), ch.c0[1] + (ax == 1 ? sg * k : 0),
+                  ch.c0[2] + (ax == 2 ? sg * k : 0));
 }
 
 // Phase 1: right-hand sides, chunk-interior elimination, reduced equations.

@@ -1772,17 +1772,23 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                     for (const WGDesc &w : t.wgs) {
                         std::fill(red.begin(), red.end(), 0.0);
                         const Chunk *chs = &t.chunks[w.chunk0];
+                        // the kernel's gather (cross-axis couplings per point), then
+                        // per chunk the along-axis couplings of its end points
                         for (int ln = 0; ln < w.nchunk; ++ln)
                             for (int k = 0; k < chs[ln].len; ++k)
-                                pt[ln * CH + k] = (D.dim == 2) ? point_rhs<double, 2>(D, c, ub, fb, chs[ln], k)
-                                                               : point_rhs<double, 3>(D, c, ub, fb, chs[ln], k);
+                                pt[ln * CH + k] = (D.dim == 2)
+                                                      ? point_rhs_across<double, 2>(D, c, ub, fb, chs[ln], k)
+                                                      : point_rhs_across<double, 3>(D, c, ub, fb, chs[ln], k);
                         for (int ln = 0; ln < w.nchunk; ++ln) {
-                            if (L.d.dim == 2)
-                                sweep_phase1<double, 2, false, true>(L.d, c, [&](int k) { return pt[ln * CH + k]; }, pt[ln * CH + chs[ln].len - 1],
-                                                                    chs[ln], ln, r, st[ln]);
-                            else
-                                sweep_phase1<double, 3, false, true>(L.d, c, [&](int k) { return pt[ln * CH + k]; }, pt[ln * CH + chs[ln].len - 1],
-                                                                    chs[ln], ln, r, st[ln]);
+                            double tb, tf;
+                            if (D.dim == 2) chunk_end_terms<double, 2>(D, c, ub, chs[ln], tb, tf);
+                            else chunk_end_terms<double, 3>(D, c, ub, chs[ln], tb, tf);
+                            const double *rp = &pt[ln * CH];
+                            const int Lc = chs[ln].len;
+                            const double rL = rp[Lc - 1] - tf - (Lc == 1 ? tb : 0.0);
+                            auto rr = [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; };
+                            if (D.dim == 2) sweep_phase1<double, 2, false, true>(D, c, rr, rL, chs[ln], ln, r, st[ln]);
+                            else sweep_phase1<double, 3, false, true>(D, c, rr, rL, chs[ln], ln, r, st[ln]);
                         }
                         for (int ln = 0; ln < w.nchunk; ++ln) rhs[ln] = r.rs[ln] + r.rn[ln];
                         reduced_solve_seq<double>(w.nchunk, &t.chunks[w.chunk0], &fac[w.chunk0], rhs.data(),

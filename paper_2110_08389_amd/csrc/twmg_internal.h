@@ -233,6 +233,6 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
 template <typename T>
 hipError_t launch_tail_cycle(const TailPlan<T> &p, T *u, const T *f, int batch, hipStream_t s);
 
-constexpr int NORM_PARTS = 1024;  // partial-maximum slots used by launch_resnorm
+constexpr int NORM_PARTS = 65536; // partial-maximum slots used by launch_resnorm
 
 } // namespace twmg
