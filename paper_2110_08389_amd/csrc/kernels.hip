@@ -246,24 +246,39 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     }
 }
 
-// The work of one workgroup descriptor w; ub / fb may point to global memory
-// or to LDS (the coarse-level kernel keeps its levels there).  All NT lanes of
-// the workgroup must call it.
-template <typename T, int DIM, int NT, bool DOFF>
+// The work of one workgroup descriptor w; all NT lanes of the workgroup must
+// call it.  REC (2D, NT/2-lane workgroups): the points are addressed through
+// the chunks' precomputed records (addrs); otherwise in general form.
+template <typename T, int DIM, int NT, bool DOFF, bool REC>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
+                                         const ChunkAddr *__restrict__ addrs, const T *__restrict__ cross,
                                          const Block *__restrict__ blocks, const WGDesc w,
                                          const NodeFac<T> *__restrict__ fac, int rings)
 {
     constexpr int PS = CH + 1; // padded row of the point staging buffer (bank-conflict free)
     __shared__ T s_pt[NT * PS + 1];
-    __shared__ Chunk s_ch[NT];
+    // chunk descriptors (general) or addressing records (REC): 16 bytes each
+    __shared__ Chunk s_ch[REC ? 1 : NT];
+    __shared__ ChunkAddr s_ca[REC ? NT : 1];
     __shared__ T s_rs[NT], s_rn[NT], s_dl[NT], s_x[NT];
     __shared__ T s_a[NT / 64], s_b[NT / 64];
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
     const int t = threadIdx.x;
     const bool act = t < w.nchunk;
-    if (act) s_ch[t] = chunks[w.chunk0 + t];
+    Chunk chl; // this lane's chunk
+    if (act) {
+        chl = chunks[w.chunk0 + t];
+        if (REC) {
+            // the record, and the chunk's cross coefficients (constant along
+            // it) in s_rs / s_rn until phase 1 reuses them
+            s_ca[t] = addrs[w.chunk0 + t];
+            s_rs[t] = cross[2 * (w.chunk0 + t)];
+            s_rn[t] = cross[2 * (w.chunk0 + t) + 1];
+        } else {
+            s_ch[t] = chl;
+        }
+    }
     __syncthreads();
     // gather: point-major over the workgroup's chunks, so that consecutive
     // lanes read consecutive points of a chunk (whole cache lines along rows)
@@ -279,10 +294,18 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 #pragma unroll
             for (int m = 0; m < GB; ++m) {
                 const int P = t + (m0 + m) * NT, c = P / CH, k = P % CH;
-                const Chunk ch = s_ch[c < w.nchunk ? c : 0];
-                const bool valid = c < w.nchunk && k < ch.len;
-                rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
-                dst[m] = valid ? c * PS + k : NT * PS;
+                const int cc = c < w.nchunk ? c : 0;
+                if (REC) {
+                    const ChunkAddr a = s_ca[cc];
+                    const bool valid = c < w.nchunk && k < (int)(a.meta & 31);
+                    rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
+                    dst[m] = valid ? c * PS + k : NT * PS;
+                } else {
+                    const Chunk ch = s_ch[cc];
+                    const bool valid = c < w.nchunk && k < ch.len;
+                    rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
+                    dst[m] = valid ? c * PS + k : NT * PS;
+                }
             }
 #pragma unroll
             for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
@@ -294,17 +317,16 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     int ext = -1;
     NodeFac<T> nf{0, 0, 0, 0};
     if (act) {
-        const Chunk ch = s_ch[t];
-        nfl = ch.nflags;
-        ext = ch.ext;
+        nfl = chl.nflags;
+        ext = chl.ext;
         nf = fac[w.chunk0 + t];
         T tb, tf;
-        chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
+        chunk_end_terms<T, DIM>(d, cf, ub, chl, tb, tf);
         const T *rp = &s_pt[t * PS];
-        const int L = ch.len;
+        const int L = chl.len;
         const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
         sweep_phase1<T, DIM, false, true, DOFF>(
-            d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, ch, t, red, st);
+            d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st);
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
@@ -315,24 +337,35 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 #pragma unroll 4
     for (int m = 0; m < CH; ++m) {
         const int P = t + m * NT, c = P / CH, k = P % CH;
-        if (c < w.nchunk && k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
+        if (c >= w.nchunk) continue;
+        if (REC) {
+            const ChunkAddr a = s_ca[c];
+            if (k < (int)(a.meta & 31)) ub[rec_slot(d, a, k)] = s_pt[c * PS + k];
+        } else {
+            if (k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
+        }
     }
 }
 
-// DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients)
+// DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients);
+// 2D workgroups of NT/2 lanes address their points through the records
 template <typename T, int DIM, int NT, bool DOFF>
 __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
-                                                    const Chunk *__restrict__ chunks, const Block *__restrict__ blocks,
+                                                    const Chunk *__restrict__ chunks,
+                                                    const ChunkAddr *__restrict__ addrs,
+                                                    const T *__restrict__ cross, const Block *__restrict__ blocks,
                                                     const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
                                                     int rings)
 {
+    constexpr bool REC = DIM == 2 && NT == twmg::NT / 2;
     const long long boff = (long long)blockIdx.y * d.bs;
-    sweep_wg<T, DIM, NT, DOFF>(d, cf, u + boff, f + boff, chunks, blocks, wgs[blockIdx.x], fac, rings);
+    sweep_wg<T, DIM, NT, DOFF, REC>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
+                                    rings);
 }
 
 template <typename T, int DIM, bool DOFF>
 static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
-                             const NodeFac<T> *fac, int batch, hipStream_t s)
+                             const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s)
 {
     const int rings = tab.rings ? 1 : 0;
     // workgroups holding a block of more than NT/2 chunks come first and run
@@ -340,10 +373,11 @@ static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, 
     // several workgroups share a CU and hide each other's memory waits
     if (tab.nwg_big > 0)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
-                           tab.chunks, tab.blocks, tab.wgs, fac, rings);
+                           tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2),
-                           0, s, d, c, u, f, tab.chunks, tab.blocks, tab.wgs + tab.nwg_big, fac, rings);
+                           0, s, d, c, u, f, tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs + tab.nwg_big, fac,
+                           rings);
 }
 
 template <typename T>
@@ -352,15 +386,21 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
 {
     if (tab.nwg == 0) return hipSuccess;
     const NodeFac<T> *fac;
-    if constexpr (sizeof(T) == 8) fac = tab.fac64[adj];
-    else fac = tab.fac32[adj];
+    const T *cross;
+    if constexpr (sizeof(T) == 8) {
+        fac = tab.fac64[adj];
+        cross = tab.cross64[adj];
+    } else {
+        fac = tab.fac32[adj];
+        cross = tab.cross32[adj];
+    }
     const bool doff = sizeof(T) == 8 && adj == 0;
     if (d.dim == 2) {
-        if (doff) launch_sweep_dim<T, 2, true>(d, c, u, f, tab, fac, batch, s);
-        else launch_sweep_dim<T, 2, false>(d, c, u, f, tab, fac, batch, s);
+        if (doff) launch_sweep_dim<T, 2, true>(d, c, u, f, tab, fac, cross, batch, s);
+        else launch_sweep_dim<T, 2, false>(d, c, u, f, tab, fac, cross, batch, s);
     } else {
-        if (doff) launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, batch, s);
-        else launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, batch, s);
+        if (doff) launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, cross, batch, s);
+        else launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, cross, batch, s);
     }
     return hipGetLastError();
 }

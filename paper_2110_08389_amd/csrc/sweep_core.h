@@ -220,6 +220,91 @@ __host__ __device__ __forceinline__ void chunk_end_terms(const Dims &d, const Co
     tf = foff ? coef_arr_rt<T, DIM>(cf, ad)[caxL] * ufw : T(0);
 }
 
+// Addressing record of a 2D chunk (host, at setup).  Returns false when the
+// chunk has more than one point whose cross neighbours are not at the regular
+// offsets (never the case for the motifs' layouts; the caller rejects it).
+inline bool make_chunk_addr(const Dims &d, const Chunk &ch, ChunkAddr &a)
+{
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int ex = ax == 0 ? sg : 0, ey = ax == 1 ? sg : 0;
+    const int qx = ax == 0 ? 0 : 1, qy = ax == 0 ? 1 : 0; // unit step across the chunk axis
+    const int plane = (d.layout != LAYOUT_ROW && col_plane(d, ch.c0[0], ch.c0[1])) ? 1 : 0;
+    const int S = plane ? d.n[1] + 1 : (int)d.st[1];
+    const bool unit = ax == plane;
+    const int dp = sg * (unit ? 1 : S), reg = unit ? S : 1;
+    const int p0 = slot32(d, ch.c0[0], ch.c0[1], 0);
+    int km = 31, kp = 31, irr_m = 0, irr_p = 0;
+    for (int k = 0; k < L; ++k) {
+        const int i = ch.c0[0] + k * ex, j = ch.c0[1] + k * ey;
+        const int p = slot32(d, i, j, 0);
+        if (p != p0 + k * dp) return false; // the chunk leaves its plane
+        const int sm = slot32(d, i - qx, j - qy, 0), sp = slot32(d, i + qx, j + qy, 0);
+        if (sm != p - reg) {
+            if (km != 31) return false;
+            km = k;
+            irr_m = sm;
+        }
+        if (sp != p + reg) {
+            if (kp != 31) return false;
+            kp = k;
+            irr_p = sp;
+        }
+    }
+    const unsigned lastinb = inblock_dirs(ch, L - 1);
+    const int qd = 2 * (1 - ax); // direction code of the cross axis toward -
+    a.p0 = p0;
+    a.irr_m = irr_m;
+    a.irr_p = irr_p;
+    a.meta = (uint32_t)L | ((uint32_t)km << 5) | ((uint32_t)kp << 10) | (((lastinb >> qd) & 1u) << 15) |
+             (((lastinb >> (qd + 1)) & 1u) << 16) | ((uint32_t)plane << 17) | ((uint32_t)ax << 18) |
+             ((uint32_t)(sg > 0) << 19);
+    return true;
+}
+
+// slot of point k of a chunk from its addressing record
+__host__ __device__ __forceinline__ int rec_slot(const Dims &d, const ChunkAddr &a, int k)
+{
+    const int plane = (a.meta >> 17) & 1, ax = (a.meta >> 18) & 1, up = (a.meta >> 19) & 1;
+    const int S = plane ? d.n[1] + 1 : (int)d.st[1];
+    const int m = ax == plane ? 1 : S;
+    return a.p0 + k * (up ? m : -m);
+}
+
+// 2D gather with the addressing record: f minus the off-block cross
+// couplings (cm toward -, cp toward +; constant along the chunk) of point k
+template <typename T>
+__host__ __device__ __forceinline__ T point_rhs_rec(const Dims &d, const ChunkAddr &a, T cm, T cp,
+                                                    const T *__restrict__ ub, const T *__restrict__ fb, int k)
+{
+    const uint32_t mt = a.meta;
+    const int L = mt & 31, km = (mt >> 5) & 31, kp = (mt >> 10) & 31;
+    const int plane = (mt >> 17) & 1, ax = (mt >> 18) & 1, up = (mt >> 19) & 1;
+    const int S = plane ? d.n[1] + 1 : (int)d.st[1];
+    const bool unit = ax == plane;
+    const int m = unit ? 1 : S, reg = unit ? S : 1;
+    const int p = a.p0 + k * (up ? m : -m);
+    const int pm = k == km ? a.irr_m : p - reg;
+    const int pp = k == kp ? a.irr_p : p + reg;
+    const bool last = k == L - 1;
+    const bool skm = last && ((mt >> 15) & 1), skp = last && ((mt >> 16) & 1);
+    T r = fb[p];
+    const T tm = cm * ub[pm], tp = cp * ub[pp];
+    r -= skm ? T(0) : tm;
+    r -= skp ? T(0) : tp;
+    return r;
+}
+
+// the chunk's cross-axis coefficients (2D): toward - and + across its axis
+template <typename T>
+__host__ __device__ __forceinline__ void chunk_cross_coefs(const Coef<T> &cf, const Chunk &ch, T &cm, T &cp)
+{
+    const int a2 = 1 - (ch.axdir >> 1);
+    const int cc = ch.c0[a2];
+    cm = cf.base[(2 * a2) * cf.cs + cc];
+    cp = cf.base[(2 * a2 + 1) * cf.cs + cc];
+}
+
 // slot of point k of a chunk
 __host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &ch, int k)
 {

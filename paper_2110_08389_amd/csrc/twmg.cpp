@@ -125,6 +125,14 @@ void motif_label(int motif, int dim, const int *n, int i, int j, int l, long lon
 struct Grid3 {
     int dim, n[3], np[3];
     long long st[3], nn;
+    int layout = LAYOUT_ROW; // storage layout of the level's arrays (chunks never straddle its planes)
+    // plane of node (i, j) in a split layout (1: column-major plane), as col_plane
+    int plane(int i, int j) const
+    {
+        if (layout == LAYOUT_ROW) return 0;
+        const int ip = std::min(i, n[0] - i), jp = std::min(j, n[1] - j);
+        return layout == LAYOUT_TWEED ? (ip > jp) : (layout == LAYOUT_WIREFRAME ? (ip < jp) : 1);
+    }
     void coords(long long p, int &i, int &j, int &l) const
     {
         i = int(p % np[0]);
@@ -156,12 +164,29 @@ int find_root(std::vector<int> &par, int x)
     return x;
 }
 
-// split a straight sequence of points into chunks of at most CH points
+// split a straight sequence of points into chunks of at most CH points that
+// each lie in one plane of the level's layout and have at most one point per
+// side whose cross neighbour is kept in the other plane (the addressing record
+// of a 2D chunk holds one such exception per side)
 void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, HostBlock &hb)
 {
     const int n = (int)pts.size();
-    const int first = (int)hb.ch.size();
-    for (int s = 0; s < n; s += CH) {
+    const int ax = axdir >> 1, qx = ax == 0 ? 0 : 1, qy = ax == 0 ? 1 : 0;
+    std::vector<int> pl(n), om(n), opp(n);
+    for (int q = 0; q < n; ++q) {
+        int i, j, l;
+        g.coords(pts[q], i, j, l);
+        pl[q] = g.plane(i, j);
+        om[q] = g.dim == 2 && g.plane(i - qx, j - qy) != pl[q];
+        opp[q] = g.dim == 2 && g.plane(i + qx, j + qy) != pl[q];
+    }
+    for (int s = 0; s < n;) {
+        int e = s + 1, cm = om[s], cp = opp[s];
+        while (e < n && e - s < CH && pl[e] == pl[s] && cm + om[e] <= 1 && cp + opp[e] <= 1) {
+            cm += om[e];
+            cp += opp[e];
+            ++e;
+        }
         Chunk c;
         std::memset(&c, 0, sizeof(c));
         int i, j, l;
@@ -169,7 +194,7 @@ void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, Hos
         c.c0[0] = (int16_t)i;
         c.c0[1] = (int16_t)j;
         c.c0[2] = (int16_t)l;
-        c.len = (uint8_t)std::min(CH, n - s);
+        c.len = (uint8_t)(e - s);
         c.axdir = (uint8_t)axdir;
         c.nextdir = (uint8_t)axdir;
         const int idx = (int)hb.ch.size();
@@ -177,11 +202,11 @@ void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, Hos
             c.flags |= CF_PREV;
             c.prev = (int16_t)(idx - 1);
         }
-        if (s + CH < n) c.flags |= CF_NEXT;
+        if (e < n) c.flags |= CF_NEXT;
         hb.ch.push_back(c);
-        hb.succ.push_back(s + CH < n ? idx + 1 : -1);
+        hb.succ.push_back(e < n ? idx + 1 : -1);
+        s = e;
     }
-    (void)first;
 }
 
 
@@ -251,11 +276,16 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
         const uint8_t m = mask[p];
         return __builtin_popcount(m) == 2 && !((m & 3) == 3 || (m & 12) == 12 || (m & 48) == 48);
     };
+    // chunks are cut where the storage plane changes (see chunk_seq); a block
+    // that would then exceed NT chunks is built without those cuts (its
+    // workgroup uses the general addressing)
+    Grid3 g_row = g;
+    g_row.layout = LAYOUT_ROW;
     for (long long r = 0; r < nn; ++r) {
         const int b = cnt[r], e = cnt[r + 1];
         if (b == e) continue;
         const int size = e - b;
-        HostBlock hb;
+        auto build_one = [&](const Grid3 &gc, HostBlock &hb) -> int {
         hb.colour = col[pts[b]];
         long long edges2 = 0;
         int nbranch = 0;
@@ -270,7 +300,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
         const long long edges = edges2 / 2;
         if (size == 1) {
             hb.type = BT_CHAIN;
-            chunk_seq(g, {pts[b]}, 1, hb);
+            chunk_seq(gc, {pts[b]}, 1, hb);
         } else if (edges == size - 1 && nbranch <= 1) {
             // tree: a straight line (chain), an L (spider with two legs) or a spider
             std::vector<std::vector<long long>> legs;
@@ -301,7 +331,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                     if (dirs[k] != dirs[k - 1]) turns.push_back((int)k);
                 if (turns.empty()) {
                     hb.type = BT_CHAIN;
-                    chunk_seq(g, path, dirs[0], hb);
+                    chunk_seq(gc, path, dirs[0], hb);
                 } else if (turns.size() == 1) {
                     const int tj = turns[0]; // path[tj] is the turning point
                     J = path[tj];
@@ -331,13 +361,32 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                     legdir.push_back(d ^ 1);
                 }
             }
+            if (J >= 0 && gc.layout != LAYOUT_ROW) {
+                // the branch point closes leg 0's chunk sequence: take as leg 0 a
+                // leg in the branch point's plane, so that no extra cut is needed
+                int i, j, l;
+                gc.coords(J, i, j, l);
+                const int pj = gc.plane(i, j);
+                auto leg_plane = [&](size_t lg) {
+                    int a, b2, c2;
+                    gc.coords(legs[lg].back(), a, b2, c2);
+                    return gc.plane(a, b2);
+                };
+                if (leg_plane(0) != pj)
+                    for (size_t lg = 1; lg < legs.size(); ++lg)
+                        if (leg_plane(lg) == pj) {
+                            std::swap(legs[0], legs[lg]);
+                            std::swap(legdir[0], legdir[lg]);
+                            break;
+                        }
+            }
             if (J >= 0) {
                 hb.type = BT_SPIDER;
                 hb.m = (int)legs.size();
                 if (hb.m > 7) return MG_EUNSUPPORTED;
                 uint8_t jmask = 0;
                 for (int lg = 1; lg < hb.m; ++lg) {
-                    chunk_seq(g, legs[lg], legdir[lg], hb);
+                    chunk_seq(gc, legs[lg], legdir[lg], hb);
                     Chunk &last = hb.ch.back();
                     last.flags |= CF_NEXT | CF_NEXT_DIRECT;
                     last.nextdir = (uint8_t)legdir[lg];
@@ -347,7 +396,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                 }
                 std::vector<long long> l0 = legs[0];
                 l0.push_back(J);
-                chunk_seq(g, l0, legdir[0], hb);
+                chunk_seq(gc, l0, legdir[0], hb);
                 hb.ch.back().flags |= CF_JUNCTION;
                 hb.ch.back().jmask = jmask;
             }
@@ -385,7 +434,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
             std::vector<int> firsts;
             for (size_t s = 0; s < sides.size(); ++s) {
                 firsts.push_back((int)hb.ch.size());
-                chunk_seq(g, sides[s], sdir[s], hb);
+                chunk_seq(gc, sides[s], sdir[s], hb);
                 Chunk &last = hb.ch.back();
                 last.flags |= CF_NEXT;
                 last.nextdir = (uint8_t)sdir[(s + 1) % sides.size()];
@@ -445,6 +494,15 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
             const int sc = hb.succ[k];
             if (sc >= 0 && hb.ch[sc].len == 1) hb.ch[k].flags |= CF_NEXT_DIRECT;
         }
+        return MG_OK;
+        };
+        HostBlock hb;
+        int rc = build_one(g, hb);
+        if (rc == MG_OK && (int)hb.ch.size() > NT && g.layout != LAYOUT_ROW) {
+            hb = HostBlock();
+            rc = build_one(g_row, hb);
+        }
+        if (rc) return rc;
         if ((int)hb.ch.size() > NT) return MG_EUNSUPPORTED;
         out.push_back(std::move(hb));
     }
@@ -455,6 +513,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
 // longest reduced solves start early).
 struct HostTable {
     std::vector<Chunk> chunks;
+    std::vector<ChunkAddr> addrs; // 2D: addressing records in the level's layout
     std::vector<Block> blocks;
     std::vector<WGDesc> wgs;  // the first nbig need NT lanes, the rest NT/2
     int nbig = 0;
@@ -1051,6 +1110,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         // keeps them in LDS in that layout)
         L.d.layout = (L.d.nn >= SPLIT_MIN_NODES) ? orient : LAYOUT_ROW;
         L.d.bs = L.d.layout == LAYOUT_ROW ? L.d.nn : 2 * L.d.nn;
+        L.g.layout = L.d.layout;
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
         for (int a = 0; a < dim; ++a) {
@@ -1120,6 +1180,23 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;
                 SweepTable &T = L.tab[s][colour];
+                if (dim == 2) {
+                    // records for the chunks of the NT/2-lane workgroups (the NT-lane
+                    // ones address their points in general form)
+                    t.addrs.assign(t.chunks.size(), ChunkAddr{0, 0, 0, 0});
+                    for (size_t wi = (size_t)t.nbig; wi < t.wgs.size(); ++wi)
+                        for (int q = t.wgs[wi].chunk0; q < t.wgs[wi].chunk0 + t.wgs[wi].nchunk; ++q)
+                            if (!make_chunk_addr(L.d, t.chunks[q], t.addrs[q])) return MG_EUNSUPPORTED;
+                    T.addrs = h->pool.upload(t.addrs, err);
+                    for (int adj = 0; adj < 2; ++adj) {
+                        std::vector<double> c64(2 * t.chunks.size());
+                        for (size_t q = 0; q < t.chunks.size(); ++q)
+                            chunk_cross_coefs<double>(L.hc64[adj], t.chunks[q], c64[2 * q], c64[2 * q + 1]);
+                        const std::vector<float> c32(c64.begin(), c64.end());
+                        T.cross64[adj] = h->pool.upload(c64, err);
+                        T.cross32[adj] = h->pool.upload(c32, err);
+                    }
+                }
                 T.chunks = h->pool.upload(t.chunks, err);
                 T.blocks = h->pool.upload(t.blocks, err);
                 T.wgs = h->pool.upload(t.wgs, err);
@@ -1774,11 +1851,18 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                         const Chunk *chs = &t.chunks[w.chunk0];
                         // the kernel's gather (cross-axis couplings per point), then
                         // per chunk the along-axis couplings of its end points
-                        for (int ln = 0; ln < w.nchunk; ++ln)
+                        // as the kernel: 2D workgroups of NT/2 lanes use the chunk
+                        // records (valid in the level's own layout only)
+                        const bool rec = D.dim == 2 && D.layout == L.d.layout && (&w - &t.wgs[0]) >= t.nbig;
+                        for (int ln = 0; ln < w.nchunk; ++ln) {
+                            double cm = 0, cp = 0;
+                            if (rec) chunk_cross_coefs<double>(c, chs[ln], cm, cp);
                             for (int k = 0; k < chs[ln].len; ++k)
-                                pt[ln * CH + k] = (D.dim == 2)
-                                                      ? point_rhs_across<double, 2>(D, c, ub, fb, chs[ln], k)
-                                                      : point_rhs_across<double, 3>(D, c, ub, fb, chs[ln], k);
+                                pt[ln * CH + k] =
+                                    rec ? point_rhs_rec<double>(D, t.addrs[w.chunk0 + ln], cm, cp, ub, fb, k)
+                                        : (D.dim == 2 ? point_rhs_across<double, 2>(D, c, ub, fb, chs[ln], k)
+                                                      : point_rhs_across<double, 3>(D, c, ub, fb, chs[ln], k));
+                        }
                         for (int ln = 0; ln < w.nchunk; ++ln) {
                             double tb, tf;
                             if (D.dim == 2) chunk_end_terms<double, 2>(D, c, ub, chs[ln], tb, tf);
@@ -1795,7 +1879,9 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                                                   dl.data(), r.x);
                         for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(&pt[ln * CH], ln, r, st[ln]);
                         for (int ln = 0; ln < w.nchunk; ++ln)
-                            for (int k = 0; k < chs[ln].len; ++k) ub[point_index(D, chs[ln], k)] = pt[ln * CH + k];
+                            for (int k = 0; k < chs[ln].len; ++k)
+                                ub[rec ? rec_slot(D, t.addrs[w.chunk0 + ln], k) : point_index(D, chs[ln], k)] =
+                                    pt[ln * CH + k];
                     }
                 }
             }

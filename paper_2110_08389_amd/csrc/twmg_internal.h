@@ -39,6 +39,22 @@ struct Chunk {
     int16_t ext;     // workgroup-local index of the branch point (leg ends) or ring border node
 };
 
+// Precomputed addressing of a 2D chunk in its level's layout.  A chunk lies
+// in one plane; along the chunk the slot moves by dp = +-1 when the chunk runs
+// along its plane's fast axis, else by +-S (S: the plane's row length), and
+// the neighbours across the chunk sit at -reg / +reg (reg = S or 1, the other
+// one).  Near the diagonal of a split layout one point per side may have its
+// cross neighbour in the other plane: point km (k_p) then reads slot irr_m
+// (irr_p).  meta bits: 0-4 len, 5-9 km, 10-14 kp (31: none), 15/16 the last
+// point's - / + cross neighbour is in the block, 17 plane (1: column-major),
+// 18 chunk axis, 19 direction (1: increasing coordinate).
+struct ChunkAddr {
+    int p0;
+    int irr_m, irr_p;
+    uint32_t meta;
+};
+static_assert(sizeof(ChunkAddr) == 16, "chunk address record is 16 bytes");
+
 // Role of a node in the reduced-system solve.  Nodes are solved by two affine
 // scans over the workgroup: forward elimination along each segment (a leg, a
 // chain, or a ring opened at its border node), then back substitution.
@@ -148,6 +164,9 @@ template <typename T> __host__ __device__ inline Coef<T> make_coef(const T *base
 
 struct SweepTable {
     Chunk *chunks = nullptr;
+    ChunkAddr *addrs = nullptr; // 2D: per-chunk addressing records
+    double *cross64[2] = {nullptr, nullptr}; // 2D: per-chunk cross coefficients (toward -, +) [fwd, transposed]
+    float *cross32[2] = {nullptr, nullptr};
     Block *blocks = nullptr;
     WGDesc *wgs = nullptr;
     NodeFac<double> *fac64[2] = {nullptr, nullptr}; // [forward, transposed operator]
