@@ -73,13 +73,16 @@ def main():
         # a plain copy of known size: FETCH_SIZE and WRITE_SIZE of its kernel
         # should each read 512 MiB; their ratio to that is the counter scale
         # an elementwise kernel (reads a, writes b once each), not the runtime's
-        # copy engine path, so the counters see ordinary vector loads and stores
-        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
+        # copy path; the views start 8 bytes into their buffers, which rules
+        # out torch's 32-byte vector accesses, so each lane moves 8 bytes as
+        # the solver's kernels do (the counters' scale depends on that)
+        n = 64 * 1024 * 1024
+        a = torch.ones(n + 1, dtype=torch.float64, device="cuda")[1:]
+        b = torch.empty(n + 1, dtype=torch.float64, device="cuda")[1:]
         for _ in range(3):
             torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.numel() * 8}))
+        print(json.dumps({"copy_bytes": n * 8}))
         return
 
     import paper_2110_08389_amd as pkg

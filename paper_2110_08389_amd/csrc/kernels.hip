@@ -114,18 +114,67 @@ static int lrow_grid(const Dims &d)
 // with the setup-time factors, so the depth is logarithmic in the block size.
 // ---------------------------------------------------------------------------
 
-// inclusive scan of affine maps x -> A x + B in lane order (composition of the
-// maps of lanes 0..t); sa/sb: per-wave totals in LDS
+// ---- wave-level building blocks of the scans -------------------------------
+// DPP row shifts move values between the 16 lanes of a row at VALU latency;
+// a lane whose source lies outside its row keeps 'old' (the identity map).
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v, double old)
+{
+    const long long vi = __builtin_bit_cast(long long, v), oi = __builtin_bit_cast(long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)vi, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(vi >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v, float old)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const long long vi = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)vi, lane), hi = __builtin_amdgcn_readlane((int)(vi >> 32), lane);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int lane)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Inclusive scan of affine maps x -> A x + B in lane order: lane t ends with
+// the composition of the maps of lanes 0..t (later maps applied last).  Rows
+// of 16 lanes by DPP shifts, the 4 rows of a wave through their totals (lane
+// reads), the waves of the workgroup through per-wave totals sa/sb in LDS.
 template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa, T *sb)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const T Ap = __shfl_up(A, o, 64), Bp = __shfl_up(B, o, 64);
-        if (lane >= o) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
+    {
+        T Ap = dpp_mov<0x111>(A, T(1)), Bp = dpp_mov<0x111>(B, T(0)); // row_shr:1
+        B = A * Bp + B;
+        A = A * Ap;
+        Ap = dpp_mov<0x112>(A, T(1));
+        Bp = dpp_mov<0x112>(B, T(0));
+        B = A * Bp + B;
+        A = A * Ap;
+        Ap = dpp_mov<0x114>(A, T(1));
+        Bp = dpp_mov<0x114>(B, T(0));
+        B = A * Bp + B;
+        A = A * Ap;
+        Ap = dpp_mov<0x118>(A, T(1));
+        Bp = dpp_mov<0x118>(B, T(0));
+        B = A * Bp + B;
+        A = A * Ap;
+    }
+    {
+        // prefixes of the rows before this lane's row
+        const T A0 = lane_value(A, 15), B0 = lane_value(B, 15);
+        const T A1 = lane_value(A, 31), B1 = lane_value(B, 31);
+        const T A2 = lane_value(A, 47), B2 = lane_value(B, 47);
+        const T P2A = A1 * A0, P2B = A1 * B0 + B1;
+        const T P3A = A2 * P2A, P3B = A2 * P2B + B2;
+        const T pA = row == 0 ? T(1) : (row == 1 ? A0 : (row == 2 ? P2A : P3A));
+        const T pB = row == 0 ? T(0) : (row == 1 ? B0 : (row == 2 ? P2B : P3B));
+        B = A * pB + B;
+        A = A * pA;
     }
     if (lane == 63) {
         sa[wv] = A;
@@ -145,14 +194,35 @@ template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa
 // the same over lanes in decreasing order (composition of the maps of lanes t..NT-1)
 template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa, T *sb)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const T An = __shfl_down(A, o, 64), Bn = __shfl_down(B, o, 64);
-        if (lane + o < 64) {
-            B = A * Bn + B;
-            A = A * An;
-        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6, row = lane >> 4;
+    {
+        T An = dpp_mov<0x101>(A, T(1)), Bn = dpp_mov<0x101>(B, T(0)); // row_shl:1
+        B = A * Bn + B;
+        A = A * An;
+        An = dpp_mov<0x102>(A, T(1));
+        Bn = dpp_mov<0x102>(B, T(0));
+        B = A * Bn + B;
+        A = A * An;
+        An = dpp_mov<0x104>(A, T(1));
+        Bn = dpp_mov<0x104>(B, T(0));
+        B = A * Bn + B;
+        A = A * An;
+        An = dpp_mov<0x108>(A, T(1));
+        Bn = dpp_mov<0x108>(B, T(0));
+        B = A * Bn + B;
+        A = A * An;
+    }
+    {
+        // suffixes of the rows after this lane's row (row totals at lanes 16 r)
+        const T A1 = lane_value(A, 16), B1 = lane_value(B, 16);
+        const T A2 = lane_value(A, 32), B2 = lane_value(B, 32);
+        const T A3 = lane_value(A, 48), B3 = lane_value(B, 48);
+        const T S2A = A2 * A3, S2B = A2 * B3 + B2;
+        const T S1A = A1 * S2A, S1B = A1 * S2B + B1;
+        const T pA = row == 3 ? T(1) : (row == 2 ? A3 : (row == 1 ? S2A : S1A));
+        const T pB = row == 3 ? T(0) : (row == 2 ? B3 : (row == 1 ? S2B : S1B));
+        B = A * pB + B;
+        A = A * pA;
     }
     if (lane == 0) {
         sa[wv] = A;
@@ -794,19 +864,41 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         const int L = ch.len;
         T tb, tf;
         chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
-        const T rL = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, L - 1) - tf - (L == 1 ? tb : T(0));
-        sweep_phase1<T, DIM, false, true>(
-            d, cf,
-            [&](int k) {
-                const T r = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
-                return k == 0 ? r - tb : r;
-            },
-            rL, ch, t, red, st);
+        if (DIM == 2) {
+            // tail levels are row-major: the lane builds its chunk's record
+            const ChunkAddr a = row_chunk_addr(d, ch);
+            T cm, cp;
+            chunk_cross_coefs<T>(cf, ch, cm, cp);
+            const T rL = point_rhs_rec<T>(d, a, cm, cp, ub, fb, L - 1) - tf - (L == 1 ? tb : T(0));
+            sweep_phase1<T, DIM, false, true>(
+                d, cf,
+                [&](int k) {
+                    const T r = point_rhs_rec<T>(d, a, cm, cp, ub, fb, k < L ? k : 0);
+                    return k == 0 ? r - tb : r;
+                },
+                rL, ch, t, red, st);
+        } else {
+            const T rL = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, L - 1) - tf - (L == 1 ? tb : T(0));
+            sweep_phase1<T, DIM, false, true>(
+                d, cf,
+                [&](int k) {
+                    const T r = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
+                    return k == 0 ? r - tb : r;
+                },
+                rL, ch, t, red, st);
+        }
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
     __syncthreads();
-    if (act) sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[point_index(d, ch, k)] = v; });
+    if (act) {
+        if (DIM == 2) {
+            const ChunkAddr a = row_chunk_addr(d, ch);
+            sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[rec_slot(d, a, k)] = v; });
+        } else {
+            sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[point_index(d, ch, k)] = v; });
+        }
+    }
 }
 
 template <typename T, int DIM>

@@ -262,6 +262,21 @@ inline bool make_chunk_addr(const Dims &d, const Chunk &ch, ChunkAddr &a)
     return true;
 }
 
+// addressing record of a 2D chunk of a row-major array (no exceptional points)
+__host__ __device__ __forceinline__ ChunkAddr row_chunk_addr(const Dims &d, const Chunk &ch)
+{
+    const int L = ch.len, ax = ch.axdir >> 1, up = ch.axdir & 1;
+    const unsigned lastinb = inblock_dirs(ch, L - 1);
+    const int qd = 2 * (1 - ax);
+    ChunkAddr a;
+    a.p0 = ch.c0[0] + ch.c0[1] * (int)d.st[1];
+    a.irr_m = 0;
+    a.irr_p = 0;
+    a.meta = (uint32_t)L | (31u << 5) | (31u << 10) | (((lastinb >> qd) & 1u) << 15) |
+             (((lastinb >> (qd + 1)) & 1u) << 16) | ((uint32_t)ax << 18) | ((uint32_t)up << 19);
+    return a;
+}
+
 // slot of point k of a chunk from its addressing record
 __host__ __device__ __forceinline__ int rec_slot(const Dims &d, const ChunkAddr &a, int k)
 {
