@@ -184,6 +184,16 @@ def timed_solve(s, f, torch, reps=3, bc=None, tol=TOL):
 def extras(pkg, inputs, torch, dev):
     """The other workloads: same GPU, stated final residuals."""
     res = {}
+    # the headline grid with the comparison smoothers (checkerboard does not
+    # converge on this stretching; it is stopped after 40 cycles)
+    f = torch.tensor(inputs.uniform((N_CELLS + 1, N_CELLS + 1), SEED), device=dev)
+    for sm, cap in (("checkerboard", 40), ("adz", 60)):
+        s = pkg.Solver([N_CELLS, N_CELLS], stretch=STRETCH, smoother=sm, max_cycles=cap, device=dev)
+        ms, st = timed_solve(s, f, torch, reps=1)
+        log("extras:", sm, st["cycles"], st["status"], f"{ms:.2f} ms")
+        res[f"{sm}_4097_V22_fp64"] = {"ms": ms, "cycles": st["cycles"], "status": st["status"],
+                                      "rel_res": st["rel_res"], "unknowns_per_s": (N_CELLS - 1) ** 2 / (ms * 1e-3)}
+        del s
     n = 2048
     f = torch.tensor(inputs.normal((n + 1, n + 1), 1002), device=dev)
     for prec in ("fp64", "fp32_ir"):

@@ -434,25 +434,44 @@ __global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__res
 }
 
 template <typename T, int DIM, bool DOFF>
-static void launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
-                             const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s)
+static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
+                                   const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s,
+                                   const SideStream &side)
 {
     const int rings = tab.rings ? 1 : 0;
     // workgroups holding a block of more than NT/2 chunks come first and run
     // with NT lanes; the rest run with NT/2 lanes (a third of the LDS), so that
-    // several workgroups share a CU and hide each other's memory waits
+    // several workgroups share a CU and hide each other's memory waits.  With
+    // a side stream the NT-lane launch overlaps the other one.
+    // the NT-lane launch goes first, on the caller's stream, so that its few
+    // large workgroups are placed before the NT/2-lane ones fill the CUs
+    const bool both = tab.nwg_big > 0 && tab.nwg > tab.nwg_big;
+    const bool fork = both && side.aux != nullptr;
+    hipStream_t ss = s;
+    if (fork) {
+        hipError_t e = hipEventRecord(side.fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side.aux, side.fork, 0);
+        if (e != hipSuccess) return e;
+        ss = side.aux;
+    }
     if (tab.nwg_big > 0)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
                            tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2),
-                           0, s, d, c, u, f, tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs + tab.nwg_big, fac,
+                           0, ss, d, c, u, f, tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs + tab.nwg_big, fac,
                            rings);
+    if (fork) {
+        hipError_t e = hipEventRecord(side.join, side.aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, side.join, 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
-                              int batch, hipStream_t s)
+                              int batch, hipStream_t s, const SideStream &side)
 {
     if (tab.nwg == 0) return hipSuccess;
     const NodeFac<T> *fac;
@@ -465,13 +484,15 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
         cross = tab.cross32[adj];
     }
     const bool doff = sizeof(T) == 8 && adj == 0;
+    hipError_t e;
     if (d.dim == 2) {
-        if (doff) launch_sweep_dim<T, 2, true>(d, c, u, f, tab, fac, cross, batch, s);
-        else launch_sweep_dim<T, 2, false>(d, c, u, f, tab, fac, cross, batch, s);
+        if (doff) e = launch_sweep_dim<T, 2, true>(d, c, u, f, tab, fac, cross, batch, s, side);
+        else e = launch_sweep_dim<T, 2, false>(d, c, u, f, tab, fac, cross, batch, s, side);
     } else {
-        if (doff) launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, cross, batch, s);
-        else launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, cross, batch, s);
+        if (doff) e = launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, cross, batch, s, side);
+        else e = launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, cross, batch, s, side);
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -607,6 +628,15 @@ __global__ void __launch_bounds__(256) k_residual_restrict(Dims fd, Dims cd, Coe
 // in the thread order of the plane that holds the rectangle, so that the loads
 // are contiguous in either layout.
 // ---------------------------------------------------------------------------
+// Workgroup w of a 1D grid of n runs on XCD w % 8 (the dispatcher deals them
+// out round-robin): give each XCD a contiguous range of tiles, so that
+// neighbouring tiles, which share their halo cache lines, meet in one L2.
+__device__ __forceinline__ int xcd_tile(int w, int n)
+{
+    const int q = n / 8, r = n % 8, x = w % 8, k = w / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // does plane C (column-major) hold node (i, j)?  (false for LAYOUT_ROW)
 __device__ __forceinline__ bool in_col(const Dims &d, int i, int j)
 {
@@ -638,10 +668,12 @@ __global__ void __launch_bounds__(256) k_restrict_tile(Dims fd, Dims cd, Coef<T>
     constexpr int CT = 16, FW = 2 * CT + 1, UW = FW + 2;
     __shared__ T su[UW * UW];
     __shared__ T sd[FW * FW];
-    const int I0 = 1 + blockIdx.x * CT, J0 = 1 + blockIdx.y * CT;
+    const int tx = (cd.n[0] - 1 + CT - 1) / CT, ty = (cd.n[1] - 1 + CT - 1) / CT;
+    const int tile = xcd_tile(blockIdx.x, tx * ty);
+    const int I0 = 1 + (tile % tx) * CT, J0 = 1 + (tile / tx) * CT;
     const int fi = 2 * I0 - 1, fj = 2 * J0 - 1; // first fine node of the defect rectangle
-    const T *ub = u + (long long)blockIdx.z * fd.bs;
-    const T *fb = f + (long long)blockIdx.z * fd.bs;
+    const T *ub = u + (long long)blockIdx.y * fd.bs;
+    const T *fb = f + (long long)blockIdx.y * fd.bs;
     const bool jf = in_col(fd, fi + CT, fj + CT);
     load_rect<T, UW, UW, UW>(fd, ub, fi - 1, fj - 1, jf, su);
     load_rect<T, FW, FW, FW>(fd, fb, fi, fj, jf, sd);
@@ -661,7 +693,7 @@ __global__ void __launch_bounds__(256) k_restrict_tile(Dims fd, Dims cd, Coef<T>
     }
     __syncthreads();
     const T w3[3] = {T(0.25), T(0.5), T(0.25)};
-    const long long cb = (long long)blockIdx.z * cd.bs;
+    const long long cb = (long long)blockIdx.y * cd.bs;
     for (int q = threadIdx.x; q < CT * CT; q += blockDim.x) {
         const int a = jf ? q / CT : q % CT, b = jf ? q % CT : q / CT;
         const int I = I0 + a, J = J0 + b;
@@ -688,9 +720,11 @@ __global__ void __launch_bounds__(256) k_prolong_tile(Dims fd, Dims cd, const T 
 {
     constexpr int FT = 32, CW = FT / 2 + 1;
     __shared__ T se[CW * CW];
-    const int i0 = blockIdx.x * FT, j0 = blockIdx.y * FT;
-    T *ub = u + (long long)blockIdx.z * fd.bs;
-    const T *eb = ec + (long long)blockIdx.z * cd.bs;
+    const int tx = (fd.n[0] + FT) / FT, ty = (fd.n[1] + FT) / FT;
+    const int tile = xcd_tile(blockIdx.x, tx * ty);
+    const int i0 = (tile % tx) * FT, j0 = (tile / tx) * FT;
+    T *ub = u + (long long)blockIdx.y * fd.bs;
+    const T *eb = ec + (long long)blockIdx.y * cd.bs;
     const bool jf = in_col(fd, i0 + FT / 2, j0 + FT / 2);
     load_rect<T, CW, CW, CW>(cd, eb, i0 / 2, j0 / 2, jf, se);
     __syncthreads();
@@ -713,7 +747,7 @@ hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T
                                     T *uc, int batch, hipStream_t s)
 {
     if (fd.dim == 2) {
-        dim3 tiles((cd.n[0] - 1 + 15) / 16, (cd.n[1] - 1 + 15) / 16, batch);
+        dim3 tiles(((cd.n[0] - 1 + 15) / 16) * ((cd.n[1] - 1 + 15) / 16), batch);
         hipLaunchKernelGGL((k_restrict_tile<T>), tiles, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
         return hipGetLastError();
     }
@@ -767,7 +801,7 @@ template <typename T>
 hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s)
 {
     if (fd.dim == 2) {
-        dim3 tiles((fd.n[0] + 1 + 31) / 32, (fd.n[1] + 1 + 31) / 32, batch);
+        dim3 tiles(((fd.n[0] + 32) / 32) * ((fd.n[1] + 32) / 32), batch);
         hipLaunchKernelGGL((k_prolong_tile<T>), tiles, dim3(256), 0, s, fd, cd, ec, u);
         return hipGetLastError();
     }
@@ -1061,7 +1095,8 @@ __global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const 
     const int tx = (d.n[0] + TS) / TS, ty = (d.n[1] + TS) / TS;
     double m = 0.0;
     bool nan = false;
-    for (int tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {
+    for (int it = blockIdx.x; it < tx * ty; it += gridDim.x) {
+        const int tile = (int)gridDim.x == tx * ty ? xcd_tile(it, tx * ty) : it;
         const int i0 = (tile % tx) * TS, j0 = (tile / tx) * TS;
         const bool jf = in_col(d, i0 + TS / 2, j0 + TS / 2);
         __syncthreads();
@@ -1312,7 +1347,7 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
 // explicit instantiations
 #define TWMG_INST(T)                                                                                                  \
     template hipError_t launch_block_sweep<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, int, \
-                                              int, hipStream_t);                                                      \
+                                              int, hipStream_t, const SideStream &);                                  \
     template hipError_t launch_checker<T>(const Dims &, const Coef<T> &, T *, const T *, int, int, hipStream_t);     \
     template hipError_t launch_residual<T>(const Dims &, const Dims &, const Coef<T> &, const T *, const T *, T *,  \
                                            int, hipStream_t);                                                         \

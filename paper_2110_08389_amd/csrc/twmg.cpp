@@ -748,6 +748,7 @@ struct mg_handle {
     mg_grid grid;
     mg_options opt;
     hipStream_t stream = nullptr;
+    SideStream side;          // overlaps big-block launches with the rest of a half-sweep
     int nlev = 0;
     Level lev[MAXLEV];
     int slot_motif[2] = {-1, -1};
@@ -1263,6 +1264,17 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double)));
     }
     if ((rc = build_tail(h))) return rc;
+    if (!h->pool.host_only) {
+        bool big = false;
+        for (int l = 0; l + 1 < h->nlev; ++l)
+            for (int sl = 0; sl < 2; ++sl)
+                for (int c = 0; c < 2; ++c) big = big || h->lev[l].tab[sl][c].nwg_big > 0;
+        if (big) {
+            HIPCHK(hipStreamCreateWithFlags(&h->side.aux, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
+        }
+    }
     h->ws_bytes = workspace_layout(h, false);
     return MG_OK;
 }
@@ -1299,7 +1311,7 @@ template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
         const int s = adj ? ns - 1 - k : k;
         for (int q = 0; q < 2; ++q) {
             const int colour = adj ? 1 - q : q;
-            HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], adj, B, h->stream));
+            HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], adj, B, h->stream, h->side));
         }
     }
     return MG_OK;
@@ -1455,6 +1467,10 @@ void mg_destroy(mg_handle *h)
     if (h->ws_owned && h->ws) (void)hipFree(h->ws);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     free_tail(h);
+    if (h->side.aux) (void)hipStreamSynchronize(h->side.aux);
+    if (h->side.fork) (void)hipEventDestroy(h->side.fork);
+    if (h->side.join) (void)hipEventDestroy(h->side.join);
+    if (h->side.aux) (void)hipStreamDestroy(h->side.aux);
     delete h;
 }
 
@@ -1725,7 +1741,8 @@ int mg_half_sweep(mg_handle *h, int lv, double *u, const double *f, int slot, in
         return MG_EINVAL;
     Level &L = h->lev[lv];
     const int adj = adjoint ? 1 : 0;
-    HIPCHK(launch_block_sweep<double>(L.d, L.c64[adj], u, f, L.tab[slot][colour], adj, h->grid.batch, h->stream));
+    HIPCHK(launch_block_sweep<double>(L.d, L.c64[adj], u, f, L.tab[slot][colour], adj, h->grid.batch, h->stream,
+                                      h->side));
     return MG_OK;
 }
 

@@ -218,9 +218,17 @@ template <typename T> struct TailPlan {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
+// Side stream for the NT-lane workgroups of a half-sweep: blocks of one colour
+// are independent, so the big-block launch runs beside the NT/2-lane one
+// (fork and join through the two events).  aux == nullptr: one stream.
+struct SideStream {
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
 template <typename T>
 hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
-                              int batch, hipStream_t s);
+                              int batch, hipStream_t s, const SideStream &side = SideStream());
 template <typename T>
 hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s);
 template <typename T>
