@@ -316,9 +316,23 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     }
 }
 
+// Orders LDS accesses of the lanes of one wavefront: a wavefront's LDS
+// instructions execute in issue order, so only the compiler has to be kept
+// from moving them across this point.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The work of one workgroup descriptor w; all NT lanes of the workgroup must
 // call it.  REC (2D, NT/2-lane workgroups): the points are addressed through
-// the chunks' precomputed records (addrs); otherwise in general form.
+// the chunks' precomputed records (addrs), and each wavefront gathers the
+// points of its own 64 chunks together with their along-axis coefficients,
+// which reach the lanes that own the chunks through the wavefront's rows of
+// the staging buffer; otherwise in general form, each lane loading its
+// chunk's coefficients itself.
 template <typename T, int DIM, int NT, bool DOFF, bool REC>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
@@ -328,9 +342,11 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 {
     constexpr int PS = CH + 1; // padded row of the point staging buffer (bank-conflict free)
     __shared__ T s_pt[NT * PS + 1];
-    // chunk descriptors (general) or addressing records (REC): 16 bytes each
+    // chunk descriptors (general) or addressing records and along-axis start
+    // coordinates (REC)
     __shared__ Chunk s_ch[REC ? 1 : NT];
     __shared__ ChunkAddr s_ca[REC ? NT : 1];
+    __shared__ int s_cx[REC ? NT : 1];
     __shared__ T s_rs[NT], s_rn[NT], s_dl[NT], s_x[NT];
     __shared__ T s_a[NT / 64], s_b[NT / 64];
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
@@ -343,6 +359,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             // the record, and the chunk's cross coefficients (constant along
             // it) in s_rs / s_rn until phase 1 reuses them
             s_ca[t] = addrs[w.chunk0 + t];
+            s_cx[t] = (chl.axdir >> 1) ? chl.c0[1] : chl.c0[0];
             s_rs[t] = cross[2 * (w.chunk0 + t)];
             s_rn[t] = cross[2 * (w.chunk0 + t) + 1];
         } else {
@@ -350,9 +367,100 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         }
     }
     __syncthreads();
-    // gather: point-major over the workgroup's chunks, so that consecutive
-    // lanes read consecutive points of a chunk (whole cache lines along rows)
-    {
+    LaneState<T> st;
+    uint8_t nfl = 0;
+    int ext = -1;
+    NodeFac<T> nf{0, 0, 0, 0};
+    if constexpr (REC) {
+        // wavefront-local gather: in step m, lane l takes point l % CH of the
+        // wavefront's chunk 4 m + l / CH (64 consecutive points per load).
+        // First the points' along-axis coefficients (a toward the predecessor,
+        // c toward the successor, and the diagonal part unless DOFF), then
+        // their right-hand sides; positions past a chunk's end repeat its
+        // first point, chunks past the workgroup's end read chunk 0 and land in
+        // the spare entry
+        const int lane = t & 63, c0w = t & ~63;
+        T av[CH], cv[CH], bv[CH];
+        int dst[CH];
+#pragma unroll
+        for (int m = 0; m < CH; ++m) {
+            const int c = c0w + 4 * m + (lane >> 4), k = lane & (CH - 1);
+            const bool inc = c < w.nchunk;
+            const int cc = inc ? c : 0;
+            const uint32_t mt = s_ca[cc].meta;
+            const int L = mt & 31, ax = (mt >> 18) & 1, up = (mt >> 19) & 1, ad = 2 * ax + up;
+            const int pos = (inc && k < L) ? s_cx[cc] + (up ? k : -k) : s_cx[cc];
+            av[m] = cf.base[(ad ^ 1) * cf.cs + pos];
+            cv[m] = cf.base[ad * cf.cs + pos];
+            bv[m] = DOFF ? T(0) : cf.base[(6 + ax) * cf.cs + pos];
+            dst[m] = inc ? c * PS + k : NT * PS;
+        }
+        // transposes through the wavefront's rows of s_pt
+        const int Lt = act ? chl.len : 1;
+        T Av[CH], Cv[CH], Bv[CH], aL, cLf, bLax = 0;
+#pragma unroll
+        for (int m = 0; m < CH; ++m) s_pt[dst[m]] = av[m];
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < CH; ++k) Av[k] = s_pt[t * PS + k];
+        aL = s_pt[t * PS + Lt - 1];
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < CH; ++m) s_pt[dst[m]] = cv[m];
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < CH; ++k) Cv[k] = s_pt[t * PS + k];
+        cLf = s_pt[t * PS + Lt - 1];
+        wave_sync();
+        if (!DOFF) {
+#pragma unroll
+            for (int m = 0; m < CH; ++m) s_pt[dst[m]] = bv[m];
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < CH; ++k) Bv[k] = s_pt[t * PS + k];
+            bLax = s_pt[t * PS + Lt - 1];
+            wave_sync();
+        } else {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) Bv[k] = T(0);
+            bLax = -(aL + cLf);
+        }
+        // right-hand sides (f minus the off-block cross couplings), in two
+        // batches whose loads are all issued before their results are stored
+        constexpr int GB = 8;
+#pragma unroll
+        for (int m0 = 0; m0 < CH; m0 += GB) {
+            T rv[GB];
+#pragma unroll
+            for (int m = 0; m < GB; ++m) {
+                const int c = c0w + 4 * (m0 + m) + (lane >> 4), k = lane & (CH - 1);
+                const bool inc = c < w.nchunk;
+                const int cc = inc ? c : 0;
+                const ChunkAddr a = s_ca[cc];
+                const bool valid = inc && k < (int)(a.meta & 31);
+                rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
+            }
+#pragma unroll
+            for (int m = 0; m < GB; ++m) s_pt[dst[m0 + m]] = rv[m];
+        }
+        // phase 1 writes s_rn of other wavefronts' chunks, which they read above
+        __syncthreads();
+        if (act) {
+            nfl = chl.nflags;
+            ext = chl.ext;
+            nf = fac[w.chunk0 + t];
+            T tb, tf;
+            chunk_end_terms_c<T, DIM>(d, ub, chl, Av[0], cLf, tb, tf);
+            const T *rp = &s_pt[t * PS];
+            const int L = chl.len;
+            const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
+            sweep_phase1_coefs<T, DIM, false, true, DOFF>(
+                d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st, Av, Cv, Bv, aL,
+                bLax);
+        }
+    } else {
+        // gather: point-major over the workgroup's chunks, so that consecutive
+        // lanes read consecutive points of a chunk (whole cache lines along rows)
         // each batch's loads are issued before any of its results is stored;
         // slots past the workgroup's points read chunk 0's first point and land
         // in the spare entry
@@ -365,38 +473,27 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             for (int m = 0; m < GB; ++m) {
                 const int P = t + (m0 + m) * NT, c = P / CH, k = P % CH;
                 const int cc = c < w.nchunk ? c : 0;
-                if (REC) {
-                    const ChunkAddr a = s_ca[cc];
-                    const bool valid = c < w.nchunk && k < (int)(a.meta & 31);
-                    rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
-                    dst[m] = valid ? c * PS + k : NT * PS;
-                } else {
-                    const Chunk ch = s_ch[cc];
-                    const bool valid = c < w.nchunk && k < ch.len;
-                    rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
-                    dst[m] = valid ? c * PS + k : NT * PS;
-                }
+                const Chunk ch = s_ch[cc];
+                const bool valid = c < w.nchunk && k < ch.len;
+                rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
+                dst[m] = valid ? c * PS + k : NT * PS;
             }
 #pragma unroll
             for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
         }
-    }
-    __syncthreads();
-    LaneState<T> st;
-    uint8_t nfl = 0;
-    int ext = -1;
-    NodeFac<T> nf{0, 0, 0, 0};
-    if (act) {
-        nfl = chl.nflags;
-        ext = chl.ext;
-        nf = fac[w.chunk0 + t];
-        T tb, tf;
-        chunk_end_terms<T, DIM>(d, cf, ub, chl, tb, tf);
-        const T *rp = &s_pt[t * PS];
-        const int L = chl.len;
-        const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
-        sweep_phase1<T, DIM, false, true, DOFF>(
-            d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st);
+        __syncthreads();
+        if (act) {
+            nfl = chl.nflags;
+            ext = chl.ext;
+            nf = fac[w.chunk0 + t];
+            T tb, tf;
+            chunk_end_terms<T, DIM>(d, cf, ub, chl, tb, tf);
+            const T *rp = &s_pt[t * PS];
+            const int L = chl.len;
+            const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
+            sweep_phase1<T, DIM, false, true, DOFF>(
+                d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st);
+        }
     }
     __syncthreads();
     reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
@@ -419,8 +516,9 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 
 // DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients);
 // 2D workgroups of NT/2 lanes address their points through the records
+// NT/2-lane workgroups: three per CU (LDS), so at most 168 VGPRs per lane
 template <typename T, int DIM, int NT, bool DOFF>
-__global__ void __launch_bounds__(NT) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+__global__ void __launch_bounds__(NT, NT == twmg::NT / 2 ? 3 : 2) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks,
                                                     const ChunkAddr *__restrict__ addrs,
                                                     const T *__restrict__ cross, const Block *__restrict__ blocks,

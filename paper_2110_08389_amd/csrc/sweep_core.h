@@ -220,6 +220,25 @@ __host__ __device__ __forceinline__ void chunk_end_terms(const Dims &d, const Co
     tf = foff ? coef_arr_rt<T, DIM>(cf, ad)[caxL] * ufw : T(0);
 }
 
+// The same with the two coefficients given: ab, the first point's coupling
+// toward its predecessor, and cf_last, the last point's toward its successor.
+template <typename T, int DIM>
+__host__ __device__ __forceinline__ void chunk_end_terms_c(const Dims &d, const T *__restrict__ ub, const Chunk &ch,
+                                                           T ab, T cf_last, T &tb, T &tf)
+{
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int e[3] = {ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0};
+    const int i0 = ch.c0[0], j0 = ch.c0[1], l0 = DIM == 3 ? ch.c0[2] : 0;
+    const int iL = i0 + (L - 1) * e[0], jL = j0 + (L - 1) * e[1], lL = l0 + (L - 1) * e[2];
+    const bool boff = !((inblock_dirs(ch, 0) >> (ad ^ 1)) & 1u);
+    const bool foff = !((inblock_dirs(ch, L - 1) >> ad) & 1u);
+    const T ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
+    const T ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
+    tb = boff ? ab * ubk : T(0);
+    tf = foff ? cf_last * ufw : T(0);
+}
+
 // Addressing record of a 2D chunk (host, at setup).  Returns false when the
 // chunk has more than one point whose cross neighbours are not at the regular
 // offsets (never the case for the motifs' layouts; the caller rejects it).
@@ -335,14 +354,18 @@ __host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &
 // rr(k) returns the right-hand side of point k (point_rhs) for k < CH - 1; it
 // is called once per k, in increasing order, so it may compute the value on
 // the spot.  rL is the right-hand side of the last point (index len - 1).
-// DIAG_FROM_OFF: the axis part of the diagonal is taken as -(a + c) instead of
-// being loaded; valid for the FP64 forward operator, whose stored diagonal
-// arrays are exactly -(lo + hi) (the same rounding), and it saves a third of
-// the lane's coefficient loads.
-template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF = false, typename RR>
-__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
-                                                      const Chunk &ch, int t, const RedArrays<T> &s,
-                                                      LaneState<T> &st)
+// The along-axis coefficients come in as values: Av[k] toward the predecessor
+// point, Cv[k] toward the successor and Bv[k] the along-axis part of the
+// diagonal, for k < CH (entries from len - 1 on are computed with but never
+// used); aL and bLax are those of the last point.
+// DIAG_FROM_OFF: the along-axis part of the diagonal is -(a + c) (Bv unused);
+// valid for the FP64 forward operator, whose stored diagonal arrays are
+// exactly -(lo + hi) (the same rounding).
+template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF, typename RR>
+__host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
+                                                            const Chunk &ch, int t, const RedArrays<T> &s,
+                                                            LaneState<T> &st, const T *Av, const T *Cv,
+                                                            const T *Bv, T aL, T bLax)
 {
     const int L = ch.len;
     const int ad = ch.axdir, ax = ad >> 1;
@@ -351,34 +374,20 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
     const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
-    const T *Pback = coef_arr_rt<T, DIM>(cf, ad ^ 1);
     const T *Pfwd = coef_arr_rt<T, DIM>(cf, ad);
     const int ex = (ax == 0) ? sg : 0, ey = (ax == 1) ? sg : 0, ez = (ax == 2) ? sg : 0;
     st.L = L;
     st.prev = ch.prev;
     st.hp = hp;
 
-    // coefficients along the chunk, all loaded before the elimination chain so
-    // that their latency is paid once: a (toward the predecessor point), c
-    // (toward the successor) and the diagonal b = along-axis part + fixed part
-    const T *Pdg = dg_arr_rt<T>(cf, ax);
+    // the diagonal b = along-axis part + fixed part (the other axes' parts)
     T bfix = 0;
     if (ax != 0) bfix += cf.dg[0][c0x];
     if (ax != 1) bfix += cf.dg[1][c0y];
     if (DIM == 3 && ax != 2) bfix += cf.dg[2][c0z];
-    T Av[CH], Cv[CH], Bv[CH];
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const int ca = (k < L) ? cax + k * sg : cax; // clamped: stays inside the arrays
-        Av[k] = Pback[ca];
-        Cv[k] = Pfwd[ca];
-        Bv[k] = DIAG_FROM_OFF ? -(Av[k] + Cv[k]) : Pdg[ca];
-    }
     // the last point's row (the node): a, b, its right-hand side, and its
     // coupling to the successor
-    const int cL_ = cax + (L - 1) * sg;
-    const T aL = Pback[cL_];
-    const T bL = (ax == 0) ? Pdg[cL_] + bfix : bfix + Pdg[cL_];
+    const T bL = (ax == 0) ? bLax + bfix : bfix + bLax;
     T cL = 0;
     if (hn) {
         const int li = c0x + (L - 1) * ex, lj = c0y + (L - 1) * ey, ll = c0z + (L - 1) * ez;
@@ -396,7 +405,8 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
 #pragma unroll
     for (int k = 0; k < CH - 1; ++k) {
         const T r = DATA ? rr(k) : T(0);
-        const T b = (ax == 0) ? Bv[k] + bfix : bfix + Bv[k];
+        const T bk = DIAG_FROM_OFF ? -(Av[k] + Cv[k]) : Bv[k];
+        const T b = (ax == 0) ? bk + bfix : bfix + bk;
         const T a = Av[k];
         const T inv = rcp<T>(b - a * Gp);
         st.G[k] = Cv[k] * inv;
@@ -443,6 +453,33 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
             s.up[ch.prev] = cprev * ww;
         }
     }
+}
+
+// Phase 1 loading the chunk's along-axis coefficients itself (one lane per
+// chunk), all before the elimination chain so that their latency is paid once.
+template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF = false, typename RR>
+__host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
+                                                      const Chunk &ch, int t, const RedArrays<T> &s,
+                                                      LaneState<T> &st)
+{
+    const int L = ch.len;
+    const int ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int cax = (ax == 0) ? ch.c0[0] : ((ax == 1) ? ch.c0[1] : ch.c0[2]);
+    const T *Pback = coef_arr_rt<T, DIM>(cf, ad ^ 1);
+    const T *Pfwd = coef_arr_rt<T, DIM>(cf, ad);
+    const T *Pdg = dg_arr_rt<T>(cf, ax);
+    T Av[CH], Cv[CH], Bv[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int ca = (k < L) ? cax + k * sg : cax; // clamped: stays inside the arrays
+        Av[k] = Pback[ca];
+        Cv[k] = Pfwd[ca];
+        Bv[k] = DIAG_FROM_OFF ? T(0) : Pdg[ca];
+    }
+    const int cL_ = cax + (L - 1) * sg;
+    sweep_phase1_coefs<T, DIM, MATRIX, DATA, DIAG_FROM_OFF>(d, cf, rr, rL, ch, t, s, st, Av, Cv, Bv, Pback[cL_],
+                                                             Pdg[cL_]);
 }
 
 // Phase 2 on the host: the reduced systems of one workgroup solved node by

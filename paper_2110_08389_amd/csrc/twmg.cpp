@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <numeric>
 #include <string>
@@ -524,38 +525,59 @@ void pack(std::vector<const HostBlock *> bl, HostTable &t)
     std::stable_sort(bl.begin(), bl.end(),
                      [](const HostBlock *a, const HostBlock *b) { return a->ch.size() > b->ch.size(); });
     // blocks of more than NT/2 chunks get a full NT-lane workgroup each; the
-    // rest are packed into NT/2-lane workgroups
+    // rest are packed into NT/2-lane workgroups by best fit in decreasing
+    // size: each block goes to the open workgroup with the least room that
+    // still holds it, so the small blocks fill the room the large ones leave
+    // (fewer, fuller workgroups: a half-empty workgroup holds a CU slot as
+    // long as a full one)
     for (int pass = 0; pass < 2; ++pass) {
         const int cap = pass == 0 ? NT : NT / 2;
         const size_t w0 = t.wgs.size();
-        WGDesc cur{0, 0, 0, 0};
-        auto flush = [&]() {
-            if (cur.nchunk) t.wgs.push_back(cur);
-            cur = WGDesc{(int)t.chunks.size(), 0, (int)t.blocks.size(), 0};
-        };
-        flush();
+        std::vector<std::vector<const HostBlock *>> groups;
+        std::multimap<int, int> room; // free chunks -> group (groups with a free block slot)
         for (const HostBlock *hb : bl) {
             const int nc = (int)hb->ch.size();
             if ((pass == 0) != (nc > NT / 2)) continue;
-            if (cur.nchunk + nc > cap || cur.nblock + 1 > cap) flush();
-            const int o = cur.nchunk;
-            for (Chunk c : hb->ch) {
-                if (c.flags & CF_PREV) c.prev = (int16_t)(c.prev + o);
-                if (c.ext >= 0) c.ext = (int16_t)(c.ext + o);
-                t.chunks.push_back(c);
+            int g = -1;
+            if (pass == 1) {
+                auto it = room.lower_bound(nc);
+                if (it != room.end()) {
+                    g = it->second;
+                    const int left = it->first - nc;
+                    room.erase(it);
+                    if ((int)groups[g].size() + 1 < cap && left > 0) room.emplace(left, g);
+                }
             }
-            Block bk;
-            std::memset(&bk, 0, sizeof(bk));
-            bk.first = (int16_t)o;
-            bk.count = (int16_t)nc;
-            bk.type = (uint8_t)hb->type;
-            bk.m = (uint8_t)hb->m;
-            for (int k = 0; k < 7; ++k) bk.ends[k] = (int16_t)(hb->ends[k] + o);
-            t.blocks.push_back(bk);
-            cur.nchunk += nc;
-            cur.nblock += 1;
+            if (g < 0) {
+                g = (int)groups.size();
+                groups.emplace_back();
+                if (pass == 1 && cap - nc > 0) room.emplace(cap - nc, g);
+            }
+            groups[g].push_back(hb);
         }
-        flush();
+        for (const auto &grp : groups) {
+            WGDesc cur{(int)t.chunks.size(), 0, (int)t.blocks.size(), 0};
+            for (const HostBlock *hb : grp) {
+                const int nc = (int)hb->ch.size();
+                const int o = cur.nchunk;
+                for (Chunk c : hb->ch) {
+                    if (c.flags & CF_PREV) c.prev = (int16_t)(c.prev + o);
+                    if (c.ext >= 0) c.ext = (int16_t)(c.ext + o);
+                    t.chunks.push_back(c);
+                }
+                Block bk;
+                std::memset(&bk, 0, sizeof(bk));
+                bk.first = (int16_t)o;
+                bk.count = (int16_t)nc;
+                bk.type = (uint8_t)hb->type;
+                bk.m = (uint8_t)hb->m;
+                for (int k = 0; k < 7; ++k) bk.ends[k] = (int16_t)(hb->ends[k] + o);
+                t.blocks.push_back(bk);
+                cur.nchunk += nc;
+                cur.nblock += 1;
+            }
+            t.wgs.push_back(cur);
+        }
         if (pass == 0) t.nbig = (int)t.wgs.size();
         // Workgroups are handed to the 8 XCDs round-robin in index order.
         // Number them so that consecutive entries of the list (blocks of
