@@ -248,12 +248,31 @@ template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa
 // back-substitutes its chunk in LDS before the point-major scatter.
 // Phase 2: the reduced systems of the workgroup's blocks (lane = node), from
 // the node rows s_rs + s_rn left by phase 1; the node values land in s_x.
+// bk is the block of index t (lanes t < w.nblock), loaded by the caller.  With
+// s_nf (4 NT entries of LDS that are free during this phase), each node
+// publishes its factors there and the branch-point and ring-border lanes read
+// them from LDS; without it they read fac.
 template <typename T>
 __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint8_t nfl, int ext, const NodeFac<T> &nf,
-                                                 const Block *__restrict__ blocks, const NodeFac<T> *__restrict__ fac,
-                                                 int rings, T *s_rs, T *s_rn, T *s_dl, T *s_x, T *s_a, T *s_b)
+                                                 const Block &bk, const NodeFac<T> *__restrict__ fac, int rings,
+                                                 T *s_rs, T *s_rn, T *s_dl, T *s_x, T *s_a, T *s_b, T *s_nf)
 {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
+    auto node_fac = [&](int q) -> NodeFac<T> {
+        if (!s_nf) return fac[w.chunk0 + q];
+        NodeFac<T> r;
+        r.alpha = s_nf[q];
+        r.inv = s_nf[nt + q];
+        r.gam = s_nf[2 * nt + q];
+        r.z = s_nf[3 * nt + q];
+        return r;
+    };
+    if (s_nf && act) {
+        s_nf[t] = nf.alpha;
+        s_nf[nt + t] = nf.inv;
+        s_nf[2 * nt + t] = nf.gam;
+        s_nf[3 * nt + t] = nf.z;
+    }
     // forward elimination along segments
     T rhs = 0, A = 0, B = 0;
     if (act) {
@@ -266,22 +285,18 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     s_dl[t] = dl;
     __syncthreads();
     // branch points of the spiders
-    if (t < w.nblock) {
-        // leg ends are read through the pointer: a private copy of the block
-        // indexed by the loop counter would live in scratch memory
-        const Block *bp = &blocks[w.block0 + t];
-        const int type = bp->type, first = bp->first, count = bp->count, m = bp->m;
-        if (type == BT_SPIDER) {
-            const int J = first + count - 1;
-            const NodeFac<T> fj = fac[w.chunk0 + J];
-            T num = s_rs[J] + s_rn[J];
-            for (int l = 1; l < m; ++l) {
-                const int e = bp->ends[l];
-                num -= fac[w.chunk0 + e].z * s_dl[e];
+    if (t < w.nblock && bk.type == BT_SPIDER) {
+        const int first = bk.first, J = first + bk.count - 1, m = bk.m;
+        const NodeFac<T> fj = node_fac(J);
+        T num = s_rs[J] + s_rn[J];
+#pragma unroll
+        for (int l = 1; l < 7; ++l)
+            if (l < m) {
+                const int e = bk.ends[l];
+                num -= node_fac(e).z * s_dl[e];
             }
-            if (J > first) num -= fj.gam * s_dl[J - 1];
-            s_x[J] = num * fj.inv;
-        }
+        if (J > first) num -= fj.gam * s_dl[J - 1];
+        s_x[J] = num * fj.inv;
     }
     __syncthreads();
     // back substitution along segments
@@ -301,13 +316,10 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     if (act && !(nfl & (NF_J | NF_B))) s_x[t] = x;
     if (rings) {
         __syncthreads();
-        if (t < w.nblock) {
-            const Block bk = blocks[w.block0 + t];
-            if (bk.type == BT_RING) {
-                const int s0 = bk.first, Bn = bk.first + bk.count - 1;
-                const NodeFac<T> fb_ = fac[w.chunk0 + Bn];
-                s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
-            }
+        if (t < w.nblock && bk.type == BT_RING) {
+            const int s0 = bk.first, Bn = bk.first + bk.count - 1;
+            const NodeFac<T> fb_ = node_fac(Bn);
+            s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
         }
         __syncthreads();
         if (act && (nfl & NF_RING)) x -= s_x[ext] * nf.z;
@@ -316,14 +328,38 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     }
 }
 
-// Orders LDS accesses of the lanes of one wavefront: a wavefront's LDS
-// instructions execute in issue order, so only the compiler has to be kept
-// from moving them across this point.
-__device__ __forceinline__ void wave_sync()
+// The along-axis coefficients of a chunk's CH positions from one coefficient
+// array P (out[k] at position cax + k for up, cax - k otherwise; entries from
+// the chunk's length on are values of neighbouring positions and go unused).
+// The CH-position window is read as CH/2 + 1 aligned pairs: the arrays start
+// at even offsets from a 16-byte aligned block with CH + 2 spare entries
+// before and after it, so every window stays inside the allocation.
+template <typename T>
+__device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int cax, int up, T (&out)[CH])
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const int lo = up ? cax : cax - (CH - 1);
+    const int e0 = lo & ~1, off = lo - e0;
+    const V2 *p2 = reinterpret_cast<const V2 *>(P + e0);
+    T W[CH + 2];
+#pragma unroll
+    for (int q = 0; q < CH / 2 + 1; ++q) {
+        const V2 v = p2[q];
+        W[2 * q] = v.x;
+        W[2 * q + 1] = v.y;
+    }
+    // selections by bit masks: written as selects between neighbouring
+    // entries, they are turned into an indexed read of W through scratch
+    // memory
+    typedef typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type U;
+    const U mo = off ? ~U(0) : U(0), mu = up ? ~U(0) : U(0);
+    auto bits = [](T v) { return __builtin_bit_cast(U, v); };
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const U a = (bits(W[k]) & ~mo) | (bits(W[k + 1]) & mo);
+        const U b = (bits(W[CH - 1 - k]) & ~mo) | (bits(W[CH - k]) & mo);
+        out[k] = __builtin_bit_cast(T, (b & ~mu) | (a & mu));
+    }
 }
 
 // The work of one workgroup descriptor w; all NT lanes of the workgroup must
@@ -370,67 +406,25 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     LaneState<T> st;
     uint8_t nfl = 0;
     int ext = -1;
+    // the lane's node factors and (lanes t < nblock) block t, for phase 2;
+    // loaded before phase 1 so that its arithmetic covers their latency
     NodeFac<T> nf{0, 0, 0, 0};
+    Block bkl;
+    bkl.type = BT_CHAIN;
     if constexpr (REC) {
-        // wavefront-local gather: in step m, lane l takes point l % CH of the
-        // wavefront's chunk 4 m + l / CH (64 consecutive points per load).
-        // First the points' along-axis coefficients (a toward the predecessor,
-        // c toward the successor, and the diagonal part unless DOFF), then
-        // their right-hand sides; positions past a chunk's end repeat its
-        // first point, chunks past the workgroup's end read chunk 0 and land in
-        // the spare entry
+        // wavefront-local gather of the right-hand sides (f minus the
+        // off-block cross couplings): in step m, lane l takes point l % CH of
+        // the wavefront's chunk 4 m + l / CH (64 consecutive points per load)
+        // and stores it in the chunk's row of s_pt.  Positions past a chunk's
+        // end repeat its first point; chunks past the workgroup's end read
+        // chunk 0 and land in the spare entry.  Two batches, each issuing all
+        // its loads before storing.
         const int lane = t & 63, c0w = t & ~63;
-        T av[CH], cv[CH], bv[CH];
-        int dst[CH];
-#pragma unroll
-        for (int m = 0; m < CH; ++m) {
-            const int c = c0w + 4 * m + (lane >> 4), k = lane & (CH - 1);
-            const bool inc = c < w.nchunk;
-            const int cc = inc ? c : 0;
-            const uint32_t mt = s_ca[cc].meta;
-            const int L = mt & 31, ax = (mt >> 18) & 1, up = (mt >> 19) & 1, ad = 2 * ax + up;
-            const int pos = (inc && k < L) ? s_cx[cc] + (up ? k : -k) : s_cx[cc];
-            av[m] = cf.base[(ad ^ 1) * cf.cs + pos];
-            cv[m] = cf.base[ad * cf.cs + pos];
-            bv[m] = DOFF ? T(0) : cf.base[(6 + ax) * cf.cs + pos];
-            dst[m] = inc ? c * PS + k : NT * PS;
-        }
-        // transposes through the wavefront's rows of s_pt
-        const int Lt = act ? chl.len : 1;
-        T Av[CH], Cv[CH], Bv[CH], aL, cLf, bLax = 0;
-#pragma unroll
-        for (int m = 0; m < CH; ++m) s_pt[dst[m]] = av[m];
-        wave_sync();
-#pragma unroll
-        for (int k = 0; k < CH; ++k) Av[k] = s_pt[t * PS + k];
-        aL = s_pt[t * PS + Lt - 1];
-        wave_sync();
-#pragma unroll
-        for (int m = 0; m < CH; ++m) s_pt[dst[m]] = cv[m];
-        wave_sync();
-#pragma unroll
-        for (int k = 0; k < CH; ++k) Cv[k] = s_pt[t * PS + k];
-        cLf = s_pt[t * PS + Lt - 1];
-        wave_sync();
-        if (!DOFF) {
-#pragma unroll
-            for (int m = 0; m < CH; ++m) s_pt[dst[m]] = bv[m];
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < CH; ++k) Bv[k] = s_pt[t * PS + k];
-            bLax = s_pt[t * PS + Lt - 1];
-            wave_sync();
-        } else {
-#pragma unroll
-            for (int k = 0; k < CH; ++k) Bv[k] = T(0);
-            bLax = -(aL + cLf);
-        }
-        // right-hand sides (f minus the off-block cross couplings), in two
-        // batches whose loads are all issued before their results are stored
         constexpr int GB = 8;
 #pragma unroll
         for (int m0 = 0; m0 < CH; m0 += GB) {
             T rv[GB];
+            int dst[GB];
 #pragma unroll
             for (int m = 0; m < GB; ++m) {
                 const int c = c0w + 4 * (m0 + m) + (lane >> 4), k = lane & (CH - 1);
@@ -439,24 +433,38 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
                 const ChunkAddr a = s_ca[cc];
                 const bool valid = inc && k < (int)(a.meta & 31);
                 rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
+                dst[m] = inc ? c * PS + k : NT * PS;
             }
 #pragma unroll
-            for (int m = 0; m < GB; ++m) s_pt[dst[m0 + m]] = rv[m];
+            for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
         }
-        // phase 1 writes s_rn of other wavefronts' chunks, which they read above
+        if (t < w.nblock) bkl = blocks[w.block0 + t];
+        // phase 1 writes s_rn of other wavefronts' chunks, which they read in
+        // the gather
         __syncthreads();
         if (act) {
             nfl = chl.nflags;
             ext = chl.ext;
             nf = fac[w.chunk0 + t];
+            // the chunk's along-axis coefficients (as aligned pairs), its
+            // neighbours outside it along its axis and its scalar coefficients
+            const int ad = chl.axdir, ax = ad >> 1, up = ad & 1, L = chl.len;
+            const int cax = ax ? chl.c0[1] : chl.c0[0], cL_ = cax + (up ? L - 1 : 1 - L);
+            T Av[CH], Cv[CH], Bv[CH], ubk, ufw;
+            chunk_coef_window<T>(cf.base + (ad ^ 1) * cf.cs, cax, up, Av);
+            chunk_coef_window<T>(cf.base + ad * cf.cs, cax, up, Cv);
+            if (!DOFF) chunk_coef_window<T>(cf.base + (6 + ax) * cf.cs, cax, up, Bv);
+            const T aL = cf.base[(ad ^ 1) * cf.cs + cL_], bLax = cf.base[(6 + ax) * cf.cs + cL_];
+            const T cLf = cf.base[ad * cf.cs + cL_];
+            chunk_end_u<T, DIM>(d, ub, chl, ubk, ufw);
+            const ChunkScalars<T> sc = chunk_scalars<T, DIM>(cf, chl);
             T tb, tf;
-            chunk_end_terms_c<T, DIM>(d, ub, chl, Av[0], cLf, tb, tf);
+            chunk_end_terms_v<T>(chl, Av[0], cLf, ubk, ufw, tb, tf);
             const T *rp = &s_pt[t * PS];
-            const int L = chl.len;
             const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
             sweep_phase1_coefs<T, DIM, false, true, DOFF>(
                 d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st, Av, Cv, Bv, aL,
-                bLax);
+                bLax, sc);
         }
     } else {
         // gather: point-major over the workgroup's chunks, so that consecutive
@@ -481,6 +489,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 #pragma unroll
             for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
         }
+        if (t < w.nblock) bkl = blocks[w.block0 + t];
         __syncthreads();
         if (act) {
             nfl = chl.nflags;
@@ -496,7 +505,8 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         }
     }
     __syncthreads();
-    reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
+    // the staging buffer is free until phase 3: it carries the node factors
+    reduced_solve_wg<T>(w, act, nfl, ext, nf, bkl, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b, s_pt);
     __syncthreads();
     if (act) sweep_phase3<T>(&s_pt[t * PS], t, red, st);
     __syncthreads();
@@ -1021,7 +1031,10 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         }
     }
     __syncthreads();
-    reduced_solve_wg<T>(w, act, nfl, ext, nf, blocks, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b);
+    Block bk;
+    bk.type = BT_CHAIN;
+    if (t < w.nblock) bk = blocks[w.block0 + t];
+    reduced_solve_wg<T>(w, act, nfl, ext, nf, bk, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b, (T *)nullptr);
     __syncthreads();
     if (act) {
         if (DIM == 2) {

@@ -220,21 +220,32 @@ __host__ __device__ __forceinline__ void chunk_end_terms(const Dims &d, const Co
     tf = foff ? coef_arr_rt<T, DIM>(cf, ad)[caxL] * ufw : T(0);
 }
 
-// The same with the two coefficients given: ab, the first point's coupling
-// toward its predecessor, and cf_last, the last point's toward its successor.
+// The chunk's two outside neighbours along its axis: ubk before the first
+// point, ufw after the last (their couplings are dropped by chunk_end_terms_v
+// when the neighbour is in the block).
 template <typename T, int DIM>
-__host__ __device__ __forceinline__ void chunk_end_terms_c(const Dims &d, const T *__restrict__ ub, const Chunk &ch,
-                                                           T ab, T cf_last, T &tb, T &tf)
+__host__ __device__ __forceinline__ void chunk_end_u(const Dims &d, const T *__restrict__ ub, const Chunk &ch, T &ubk,
+                                                     T &ufw)
 {
-    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
-    const int sg = (ad & 1) ? 1 : -1;
+    const int L = ch.len, ax = ch.axdir >> 1;
+    const int sg = (ch.axdir & 1) ? 1 : -1;
     const int e[3] = {ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0};
     const int i0 = ch.c0[0], j0 = ch.c0[1], l0 = DIM == 3 ? ch.c0[2] : 0;
     const int iL = i0 + (L - 1) * e[0], jL = j0 + (L - 1) * e[1], lL = l0 + (L - 1) * e[2];
+    ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
+    ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
+}
+
+// chunk_end_terms from the loaded neighbours and the two coefficients: ab, the
+// first point's coupling toward its predecessor, and cf_last, the last
+// point's toward its successor.
+template <typename T>
+__host__ __device__ __forceinline__ void chunk_end_terms_v(const Chunk &ch, T ab, T cf_last, T ubk, T ufw, T &tb,
+                                                           T &tf)
+{
+    const int L = ch.len, ad = ch.axdir;
     const bool boff = !((inblock_dirs(ch, 0) >> (ad ^ 1)) & 1u);
     const bool foff = !((inblock_dirs(ch, L - 1) >> ad) & 1u);
-    const T ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
-    const T ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
     tb = boff ? ab * ubk : T(0);
     tf = foff ? cf_last * ufw : T(0);
 }
@@ -361,11 +372,39 @@ __host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &
 // DIAG_FROM_OFF: the along-axis part of the diagonal is -(a + c) (Bv unused);
 // valid for the FP64 forward operator, whose stored diagonal arrays are
 // exactly -(lo + hi) (the same rounding).
+// The chunk's scalar coefficients used by phase 1: the fixed part of the
+// diagonal (the other axes' parts, constant along the chunk), the last
+// point's coupling to its successor (cL, 0 without one) and the first point's
+// predecessor's coupling back to it (cprev, 0 without a predecessor).
+template <typename T> struct ChunkScalars {
+    T bfix, cL, cprev;
+};
+template <typename T, int DIM>
+__host__ __device__ __forceinline__ ChunkScalars<T> chunk_scalars(const Coef<T> &cf, const Chunk &ch)
+{
+    const int L = ch.len;
+    const int ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
+    const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
+    ChunkScalars<T> r{0, 0, 0};
+    if (ax != 0) r.bfix += cf.dg[0][c0x];
+    if (ax != 1) r.bfix += cf.dg[1][c0y];
+    if (DIM == 3 && ax != 2) r.bfix += cf.dg[2][c0z];
+    if (ch.flags & CF_NEXT) {
+        const int nx = ch.nextdir, na = nx >> 1;
+        const int cn = (na == 0 ? c0x : (na == 1 ? c0y : c0z)) + (na == ax ? (L - 1) * sg : 0);
+        r.cL = coef_arr_rt<T, DIM>(cf, nx)[cn];
+    }
+    if ((ch.flags & CF_PREV) && L >= 2) r.cprev = coef_arr_rt<T, DIM>(cf, ad)[cax - sg];
+    return r;
+}
+
 template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF, typename RR>
 __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
                                                             const Chunk &ch, int t, const RedArrays<T> &s,
                                                             LaneState<T> &st, const T *Av, const T *Cv,
-                                                            const T *Bv, T aL, T bLax)
+                                                            const T *Bv, T aL, T bLax, const ChunkScalars<T> &sc)
 {
     const int L = ch.len;
     const int ad = ch.axdir, ax = ad >> 1;
@@ -374,30 +413,23 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
     const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
     const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
-    const T *Pfwd = coef_arr_rt<T, DIM>(cf, ad);
     const int ex = (ax == 0) ? sg : 0, ey = (ax == 1) ? sg : 0, ez = (ax == 2) ? sg : 0;
     st.L = L;
     st.prev = ch.prev;
     st.hp = hp;
 
     // the diagonal b = along-axis part + fixed part (the other axes' parts)
-    T bfix = 0;
-    if (ax != 0) bfix += cf.dg[0][c0x];
-    if (ax != 1) bfix += cf.dg[1][c0y];
-    if (DIM == 3 && ax != 2) bfix += cf.dg[2][c0z];
+    const T bfix = sc.bfix;
     // the last point's row (the node): a, b, its right-hand side, and its
     // coupling to the successor
     const T bL = (ax == 0) ? bLax + bfix : bfix + bLax;
-    T cL = 0;
-    if (hn) {
+    const T cL = sc.cL;
+    if (MATRIX && hn && nd) {
+        // the successor's row coefficient back toward this point
         const int li = c0x + (L - 1) * ex, lj = c0y + (L - 1) * ey, ll = c0z + (L - 1) * ez;
         const int nx = ch.nextdir, na = nx >> 1, ns = (nx & 1) ? 1 : -1;
         const int cn = (na == 0) ? li : ((na == 1) ? lj : ll);
-        cL = coef_arr_rt<T, DIM>(cf, nx)[cn];
-        if (MATRIX && nd) {
-            // the successor's row coefficient back toward this point
-            s.aux[t] = coef_arr_rt<T, DIM>(cf, nx ^ 1)[cn + ns];
-        }
+        s.aux[t] = coef_arr_rt<T, DIM>(cf, nx ^ 1)[cn + ns];
     }
     // elimination of the interior (points 0..L-2) with zero end values; run
     // branch-free over all CH positions, entries from L-1 on are not used
@@ -446,7 +478,7 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
         }
     }
     if (hp && L >= 2) {
-        const T cprev = Pfwd[cax - sg];
+        const T cprev = sc.cprev;
         if (DATA) s.rn[ch.prev] = -cprev * y;
         if (MATRIX) {
             s.dn[ch.prev] = cprev * v;
@@ -479,7 +511,7 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     }
     const int cL_ = cax + (L - 1) * sg;
     sweep_phase1_coefs<T, DIM, MATRIX, DATA, DIAG_FROM_OFF>(d, cf, rr, rL, ch, t, s, st, Av, Cv, Bv, Pback[cL_],
-                                                             Pdg[cL_]);
+                                                             Pdg[cL_], chunk_scalars<T, DIM>(cf, ch));
 }
 
 // Phase 2 on the host: the reduced systems of one workgroup solved node by

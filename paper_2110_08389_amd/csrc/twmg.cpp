@@ -1157,8 +1157,11 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     // neighbours toward p: lo^T_i = hi_{i-1}, hi^T_i = lo_{i+1}.
     for (int l = 0; l < nl; ++l) {
         Level &L = h->lev[l];
+        // arrays of an even number of entries, so that each starts 16-byte
+        // aligned in the device block (the sweep reads coefficient pairs)
         long long cs = 1;
         for (int a = 0; a < dim; ++a) cs = std::max(cs, (long long)L.d.n[a] + 1);
+        cs += cs & 1;
         L.cs = cs;
         for (int o = 0; o < 2; ++o) L.hblk[o].assign(9 * cs, 0.0);
         for (int a = 0; a < dim; ++a) {
@@ -1177,12 +1180,17 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         }
         int err = 0;
         for (int o = 0; o < 2; ++o) {
-            const std::vector<float> b32(L.hblk[o].begin(), L.hblk[o].end());
-            const double *p64 = h->pool.upload(L.hblk[o], err);
+            // the device blocks carry COEF_PAD spare (zero) entries on both
+            // sides: the sweep reads whole windows of CH + 2 entries around
+            // a chunk, which may reach past the first or last array
+            std::vector<double> b64(2 * COEF_PAD + L.hblk[o].size(), 0.0);
+            std::copy(L.hblk[o].begin(), L.hblk[o].end(), b64.begin() + COEF_PAD);
+            const std::vector<float> b32(b64.begin(), b64.end());
+            const double *p64 = h->pool.upload(b64, err);
             const float *p32 = h->pool.upload(b32, err);
             if (err) return err;
-            L.c64[o] = make_coef<double>(p64, cs);
-            L.c32[o] = make_coef<float>(p32, cs);
+            L.c64[o] = make_coef<double>(p64 ? p64 + COEF_PAD : nullptr, cs);
+            L.c32[o] = make_coef<float>(p32 ? p32 + COEF_PAD : nullptr, cs);
             L.hc64[o] = make_coef<double>(L.hblk[o].data(), cs);
         }
     }

@@ -12,6 +12,9 @@ namespace twmg {
 // at most NT chunks of at most CH points each.
 constexpr int NT = 512;
 constexpr int CH = 16;
+// spare entries on each side of a device coefficient block (a multiple of 2,
+// at least the CH + 2 entries of a chunk's coefficient window)
+constexpr int COEF_PAD = CH + 2;
 
 // Direction codes: d = 2*axis + (positive ? 1 : 0); the reverse is d ^ 1.
 __host__ __device__ inline int dir_axis(int d) { return d >> 1; }
