@@ -328,6 +328,16 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
     }
 }
 
+// Orders LDS accesses of the lanes of one wavefront: a wavefront's LDS
+// instructions execute in issue order, so only the compiler has to be kept
+// from moving them across this point.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The along-axis coefficients of a chunk's CH positions from one coefficient
 // array P (out[k] at position cax + k for up, cax - k otherwise; entries from
 // the chunk's length on are values of neighbouring positions and go unused).
@@ -402,7 +412,14 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             s_ch[t] = chl;
         }
     }
-    __syncthreads();
+    // REC: each wavefront gathers only its own chunks, whose records and
+    // cross coefficients its own lanes wrote (positions past the workgroup's
+    // end use the wavefront's first chunk; a wavefront without chunks skips
+    // the gather)
+    if (REC)
+        wave_sync();
+    else
+        __syncthreads();
     LaneState<T> st;
     uint8_t nfl = 0;
     int ext = -1;
@@ -416,27 +433,29 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         // off-block cross couplings): in step m, lane l takes point l % CH of
         // the wavefront's chunk 4 m + l / CH (64 consecutive points per load)
         // and stores it in the chunk's row of s_pt.  Positions past a chunk's
-        // end repeat its first point; chunks past the workgroup's end read
-        // chunk 0 and land in the spare entry.  Two batches, each issuing all
-        // its loads before storing.
+        // end repeat its first point; chunks past the workgroup's end read the
+        // wavefront's first chunk and land in the spare entry.  Two batches,
+        // each issuing all its loads before storing.
         const int lane = t & 63, c0w = t & ~63;
         constexpr int GB = 8;
+        if (c0w < w.nchunk) {
 #pragma unroll
-        for (int m0 = 0; m0 < CH; m0 += GB) {
-            T rv[GB];
-            int dst[GB];
+            for (int m0 = 0; m0 < CH; m0 += GB) {
+                T rv[GB];
+                int dst[GB];
 #pragma unroll
-            for (int m = 0; m < GB; ++m) {
-                const int c = c0w + 4 * (m0 + m) + (lane >> 4), k = lane & (CH - 1);
-                const bool inc = c < w.nchunk;
-                const int cc = inc ? c : 0;
-                const ChunkAddr a = s_ca[cc];
-                const bool valid = inc && k < (int)(a.meta & 31);
-                rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
-                dst[m] = inc ? c * PS + k : NT * PS;
+                for (int m = 0; m < GB; ++m) {
+                    const int c = c0w + 4 * (m0 + m) + (lane >> 4), k = lane & (CH - 1);
+                    const bool inc = c < w.nchunk;
+                    const int cc = inc ? c : c0w;
+                    const ChunkAddr a = s_ca[cc];
+                    const bool valid = inc && k < (int)(a.meta & 31);
+                    rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
+                    dst[m] = inc ? c * PS + k : NT * PS;
+                }
+#pragma unroll
+                for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
             }
-#pragma unroll
-            for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
         }
         if (t < w.nblock) bkl = blocks[w.block0 + t];
         // phase 1 writes s_rn of other wavefronts' chunks, which they read in
@@ -509,16 +528,37 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     reduced_solve_wg<T>(w, act, nfl, ext, nf, bkl, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b, s_pt);
     __syncthreads();
     if (act) sweep_phase3<T>(&s_pt[t * PS], t, red, st);
-    __syncthreads();
-    // scatter, point-major like the gather
+    if constexpr (REC) {
+        // scatter over the wavefront's own chunks (it reads only its own rows,
+        // so a wavefront-level order suffices), point-major like the gather;
+        // every slot and value is read before the stores, which are masked
+        // rather than branched
+        wave_sync();
+        const int lane = t & 63, c0w = t & ~63;
+        const int cfb = c0w < w.nchunk ? c0w : 0;
+        int slot[CH];
+        T val[CH];
+        bool ok[CH];
+#pragma unroll
+        for (int m = 0; m < CH; ++m) {
+            const int c = c0w + 4 * m + (lane >> 4), k = lane & (CH - 1);
+            const bool inc = c < w.nchunk;
+            const int cc = inc ? c : cfb;
+            const ChunkAddr a = s_ca[cc];
+            ok[m] = inc && k < (int)(a.meta & 31);
+            slot[m] = rec_slot(d, a, ok[m] ? k : 0);
+            val[m] = s_pt[cc * PS + k];
+        }
+#pragma unroll
+        for (int m = 0; m < CH; ++m)
+            if (ok[m]) ub[slot[m]] = val[m];
+    } else {
+        __syncthreads();
+        // scatter, point-major like the gather
 #pragma unroll 4
-    for (int m = 0; m < CH; ++m) {
-        const int P = t + m * NT, c = P / CH, k = P % CH;
-        if (c >= w.nchunk) continue;
-        if (REC) {
-            const ChunkAddr a = s_ca[c];
-            if (k < (int)(a.meta & 31)) ub[rec_slot(d, a, k)] = s_pt[c * PS + k];
-        } else {
+        for (int m = 0; m < CH; ++m) {
+            const int P = t + m * NT, c = P / CH, k = P % CH;
+            if (c >= w.nchunk) continue;
             if (k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
         }
     }
