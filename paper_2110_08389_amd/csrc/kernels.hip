@@ -470,13 +470,13 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             const int ad = chl.axdir, ax = ad >> 1, up = ad & 1, L = chl.len;
             const int cax = ax ? chl.c0[1] : chl.c0[0], cL_ = cax + (up ? L - 1 : 1 - L);
             T Av[CH], Cv[CH], Bv[CH], ubk, ufw;
-            chunk_coef_window<T>(cf.base + (ad ^ 1) * cf.cs, cax, up, Av);
-            chunk_coef_window<T>(cf.base + ad * cf.cs, cax, up, Cv);
-            if (!DOFF) chunk_coef_window<T>(cf.base + (6 + ax) * cf.cs, cax, up, Bv);
             const T aL = cf.base[(ad ^ 1) * cf.cs + cL_], bLax = cf.base[(6 + ax) * cf.cs + cL_];
             const T cLf = cf.base[ad * cf.cs + cL_];
             chunk_end_u<T, DIM>(d, ub, chl, ubk, ufw);
             const ChunkScalars<T> sc = chunk_scalars<T, DIM>(cf, chl);
+            chunk_coef_window<T>(cf.base + (ad ^ 1) * cf.cs, cax, up, Av);
+            chunk_coef_window<T>(cf.base + ad * cf.cs, cax, up, Cv);
+            if (!DOFF) chunk_coef_window<T>(cf.base + (6 + ax) * cf.cs, cax, up, Bv);
             T tb, tf;
             chunk_end_terms_v<T>(chl, Av[0], cLf, ubk, ufw, tb, tf);
             const T *rp = &s_pt[t * PS];

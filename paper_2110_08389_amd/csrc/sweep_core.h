@@ -387,16 +387,19 @@ __host__ __device__ __forceinline__ ChunkScalars<T> chunk_scalars(const Coef<T> 
     const int sg = (ad & 1) ? 1 : -1;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
     const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
+    // every load is made unconditionally (all indices are valid positions)
+    // and the unused ones are dropped by selects, so that the loads issue
+    // together
+    const T g0 = cf.dg[0][c0x], g1 = cf.dg[1][c0y], g2 = (DIM == 3) ? cf.dg[2][c0z] : T(0);
     ChunkScalars<T> r{0, 0, 0};
-    if (ax != 0) r.bfix += cf.dg[0][c0x];
-    if (ax != 1) r.bfix += cf.dg[1][c0y];
-    if (DIM == 3 && ax != 2) r.bfix += cf.dg[2][c0z];
-    if (ch.flags & CF_NEXT) {
-        const int nx = ch.nextdir, na = nx >> 1;
-        const int cn = (na == 0 ? c0x : (na == 1 ? c0y : c0z)) + (na == ax ? (L - 1) * sg : 0);
-        r.cL = coef_arr_rt<T, DIM>(cf, nx)[cn];
-    }
-    if ((ch.flags & CF_PREV) && L >= 2) r.cprev = coef_arr_rt<T, DIM>(cf, ad)[cax - sg];
+    r.bfix = T(0) + (ax != 0 ? g0 : g1);
+    if (DIM == 3) r.bfix += (ax == 2 ? g1 : g2);
+    const int nx = ch.nextdir, na = nx >> 1;
+    const int cn = (na == 0 ? c0x : (na == 1 ? c0y : c0z)) + (na == ax ? (L - 1) * sg : 0);
+    const T cLv = coef_arr_rt<T, DIM>(cf, nx)[cn];
+    const T cpv = coef_arr_rt<T, DIM>(cf, ad)[cax - sg];
+    r.cL = (ch.flags & CF_NEXT) ? cLv : T(0);
+    r.cprev = ((ch.flags & CF_PREV) && L >= 2) ? cpv : T(0);
     return r;
 }
 
