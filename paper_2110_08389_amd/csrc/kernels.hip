@@ -566,16 +566,17 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 
 // DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients);
 // 2D workgroups of NT/2 lanes address their points through the records
-// NT/2-lane workgroups: three per CU (LDS), so at most 168 VGPRs per lane
+// Workgroups of at most NT/2 lanes: at least three waves per SIMD, so at most
+// 168 VGPRs per lane
 template <typename T, int DIM, int NT, bool DOFF>
-__global__ void __launch_bounds__(NT, NT == twmg::NT / 2 ? 3 : 2) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
+__global__ void __launch_bounds__(NT, NT <= twmg::NT / 2 ? 3 : 2) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks,
                                                     const ChunkAddr *__restrict__ addrs,
                                                     const T *__restrict__ cross, const Block *__restrict__ blocks,
                                                     const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
                                                     int rings)
 {
-    constexpr bool REC = DIM == 2 && NT == twmg::NT / 2;
+    constexpr bool REC = DIM == 2 && NT <= twmg::NT / 2;
     const long long boff = (long long)blockIdx.y * d.bs;
     sweep_wg<T, DIM, NT, DOFF, REC>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
                                     rings);
@@ -605,10 +606,28 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
     if (tab.nwg_big > 0)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
                            tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
-    if (tab.nwg > tab.nwg_big)
-        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), dim3(tab.nwg - tab.nwg_big, batch), dim3(NT / 2),
-                           0, ss, d, c, u, f, tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs + tab.nwg_big, fac,
-                           rings);
+    if (tab.nwg > tab.nwg_big) {
+        const dim3 grid(tab.nwg - tab.nwg_big, batch);
+        const WGDesc *wsm = tab.wgs + tab.nwg_big;
+        if (tab.nts == NT / 2) {
+            hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, ss, d, c, u, f,
+                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+        } else {
+            if constexpr (DIM == 2) {
+                // narrow workgroups (2D levels bound by a workgroup's latency)
+                if (tab.nts == 64)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 128)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF>), grid, dim3(128), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else
+                    return hipErrorInvalidValue;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        }
+    }
     if (fork) {
         hipError_t e = hipEventRecord(side.join, side.aux);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, side.join, 0);

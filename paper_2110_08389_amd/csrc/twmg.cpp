@@ -516,11 +516,16 @@ struct HostTable {
     std::vector<Chunk> chunks;
     std::vector<ChunkAddr> addrs; // 2D: addressing records in the level's layout
     std::vector<Block> blocks;
-    std::vector<WGDesc> wgs;  // the first nbig need NT lanes, the rest NT/2
+    std::vector<WGDesc> wgs;  // the first nbig need NT lanes, the rest nts
     int nbig = 0;
+    int nts = NT / 2;         // lanes of the small workgroups (64, 128 or NT/2)
 };
 
-void pack(std::vector<const HostBlock *> bl, HostTable &t)
+// Pack the blocks of one colour.  narrow: the small workgroups may be
+// narrower than NT/2 lanes (64 or 128, the narrowest that holds the largest
+// small block): more, shorter workgroups for levels whose sweeps are bound by
+// a workgroup's latency rather than by bandwidth.
+void pack(std::vector<const HostBlock *> bl, HostTable &t, bool narrow = false)
 {
     std::stable_sort(bl.begin(), bl.end(),
                      [](const HostBlock *a, const HostBlock *b) { return a->ch.size() > b->ch.size(); });
@@ -530,8 +535,14 @@ void pack(std::vector<const HostBlock *> bl, HostTable &t)
     // still holds it, so the small blocks fill the room the large ones leave
     // (fewer, fuller workgroups: a half-empty workgroup holds a CU slot as
     // long as a full one)
+    int maxsmall = 1;
+    for (const HostBlock *hb : bl)
+        if ((int)hb->ch.size() <= NT / 2) maxsmall = std::max(maxsmall, (int)hb->ch.size());
+    t.nts = NT / 2;
+    if (narrow)
+        while (t.nts > 64 && maxsmall <= t.nts / 2) t.nts /= 2;
     for (int pass = 0; pass < 2; ++pass) {
-        const int cap = pass == 0 ? NT : NT / 2;
+        const int cap = pass == 0 ? NT : t.nts;
         const size_t w0 = t.wgs.size();
         std::vector<std::vector<const HostBlock *>> groups;
         std::multimap<int, int> room; // free chunks -> group (groups with a free block slot)
@@ -606,7 +617,7 @@ bool validate(const Grid3 &g, const HostTable &t)
     const int nc = (int)t.chunks.size(), nb = (int)t.blocks.size();
     for (size_t wi = 0; wi < t.wgs.size(); ++wi) {
         const WGDesc &w = t.wgs[wi];
-        const int cap = ((int)wi < t.nbig) ? NT : NT / 2;
+        const int cap = ((int)wi < t.nbig) ? NT : t.nts;
         if (w.chunk0 < 0 || w.nchunk < 1 || w.nchunk > cap || w.chunk0 + w.nchunk > nc) return false;
         if (w.block0 < 0 || w.nblock < 1 || w.nblock > cap || w.block0 + w.nblock > nb) return false;
         for (int k = 0; k < w.nchunk; ++k) {
@@ -1055,7 +1066,8 @@ int build_tail(mg_handle *h)
     for (int l = nl - 2; l >= 0; --l) {
         bool fits = h->lev[l].d.layout == LAYOUT_ROW;
         for (int sl = 0; sl < 2; ++sl)
-            for (int c = 0; c < 2; ++c) fits = fits && h->lev[l].tab[sl][c].nwg_big == 0;
+            for (int c = 0; c < 2; ++c)
+                fits = fits && h->lev[l].tab[sl][c].nwg_big == 0 && h->lev[l].tab[sl][c].nts == NT / 2;
         std::vector<unsigned char> img;
         TailPlan<double> p;
         if (!fits || tail_image<double>(h, l, 0, img, p) > (size_t)TAIL_BYTES) break;
@@ -1207,12 +1219,16 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 for (const HostBlock &hb : blocks)
                     if (hb.colour == colour) sel.push_back(&hb);
                 HostTable &t = L.htab[s][colour];
-                pack(sel, t);
+                // narrow workgroups for 2D levels too large for the
+                // coarse-level kernel (whose sweeps use NT/2 lanes)
+                const bool narrow = dim == 2 && L.d.nn * 2 * (long long)sizeof(double) > TAIL_BYTES &&
+                                    !std::getenv("TWMG_WIDE_WG");
+                pack(sel, t, narrow);
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;
                 SweepTable &T = L.tab[s][colour];
                 if (dim == 2) {
-                    // records for the chunks of the NT/2-lane workgroups (the NT-lane
+                    // records for the chunks of the small workgroups (the NT-lane
                     // ones address their points in general form)
                     t.addrs.assign(t.chunks.size(), ChunkAddr{0, 0, 0, 0});
                     for (size_t wi = (size_t)t.nbig; wi < t.wgs.size(); ++wi)
@@ -1233,6 +1249,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 T.wgs = h->pool.upload(t.wgs, err);
                 T.nwg = (int)t.wgs.size();
                 T.nwg_big = t.nbig;
+                T.nts = t.nts;
                 T.nchunk = (int)t.chunks.size();
                 T.nblock = (int)t.blocks.size();
                 for (const Block &bk : t.blocks)

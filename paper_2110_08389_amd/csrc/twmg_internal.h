@@ -175,7 +175,8 @@ struct SweepTable {
     NodeFac<double> *fac64[2] = {nullptr, nullptr}; // [forward, transposed operator]
     NodeFac<float> *fac32[2] = {nullptr, nullptr};
     int nwg = 0, nchunk = 0, nblock = 0;
-    int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others at most NT/2
+    int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others nts
+    int nts = NT / 2; // lanes of the small workgroups: 64, 128 or NT/2 (2D only below NT/2)
     bool rings = false;
 };
 
