@@ -441,7 +441,9 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         if (c0w < w.nchunk) {
 #pragma unroll
             for (int m0 = 0; m0 < CH; m0 += GB) {
-                T rv[GB];
+                // all of a batch's loads are issued before any is used
+                T fv[GB], um[GB], upv[GB], cm[GB], cp[GB];
+                bool skm[GB], skp[GB];
                 int dst[GB];
 #pragma unroll
                 for (int m = 0; m < GB; ++m) {
@@ -450,11 +452,22 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
                     const int cc = inc ? c : c0w;
                     const ChunkAddr a = s_ca[cc];
                     const bool valid = inc && k < (int)(a.meta & 31);
-                    rv[m] = point_rhs_rec<T>(d, a, s_rs[cc], s_rn[cc], ub, fb, valid ? k : 0);
+                    const RecSlots q = rec_point_slots(d, a, valid ? k : 0);
+                    fv[m] = fb[q.p];
+                    um[m] = ub[q.pm];
+                    upv[m] = ub[q.pp];
+                    skm[m] = q.skm;
+                    skp[m] = q.skp;
+                    cm[m] = s_rs[cc];
+                    cp[m] = s_rn[cc];
                     dst[m] = inc ? c * PS + k : NT * PS;
                 }
+                // keep the scheduler from starting the arithmetic (and its
+                // waits) before the batch's last load has issued
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int m = 0; m < GB; ++m) s_pt[dst[m]] = rv[m];
+                for (int m = 0; m < GB; ++m)
+                    s_pt[dst[m]] = rec_rhs_combine<T>(fv[m], um[m], upv[m], cm[m], cp[m], skm[m], skp[m]);
             }
         }
         if (t < w.nblock) bkl = blocks[w.block0 + t];

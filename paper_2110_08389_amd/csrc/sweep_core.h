@@ -318,9 +318,13 @@ __host__ __device__ __forceinline__ int rec_slot(const Dims &d, const ChunkAddr 
 
 // 2D gather with the addressing record: f minus the off-block cross
 // couplings (cm toward -, cp toward +; constant along the chunk) of point k
-template <typename T>
-__host__ __device__ __forceinline__ T point_rhs_rec(const Dims &d, const ChunkAddr &a, T cm, T cp,
-                                                    const T *__restrict__ ub, const T *__restrict__ fb, int k)
+// The slots point k reads (its own, p, and its cross neighbours pm, pp) and
+// whether the last point's neighbours are in the block (skm, skp).
+struct RecSlots {
+    int p, pm, pp;
+    bool skm, skp;
+};
+__host__ __device__ __forceinline__ RecSlots rec_point_slots(const Dims &d, const ChunkAddr &a, int k)
 {
     const uint32_t mt = a.meta;
     const int L = mt & 31, km = (mt >> 5) & 31, kp = (mt >> 10) & 31;
@@ -328,16 +332,33 @@ __host__ __device__ __forceinline__ T point_rhs_rec(const Dims &d, const ChunkAd
     const int S = plane ? d.n[1] + 1 : (int)d.st[1];
     const bool unit = ax == plane;
     const int m = unit ? 1 : S, reg = unit ? S : 1;
-    const int p = a.p0 + k * (up ? m : -m);
-    const int pm = k == km ? a.irr_m : p - reg;
-    const int pp = k == kp ? a.irr_p : p + reg;
+    RecSlots r;
+    r.p = a.p0 + k * (up ? m : -m);
+    r.pm = k == km ? a.irr_m : r.p - reg;
+    r.pp = k == kp ? a.irr_p : r.p + reg;
     const bool last = k == L - 1;
-    const bool skm = last && ((mt >> 15) & 1), skp = last && ((mt >> 16) & 1);
-    T r = fb[p];
-    const T tm = cm * ub[pm], tp = cp * ub[pp];
+    r.skm = last && ((mt >> 15) & 1);
+    r.skp = last && ((mt >> 16) & 1);
+    return r;
+}
+
+// f minus the two cross couplings, from the loaded values
+template <typename T>
+__host__ __device__ __forceinline__ T rec_rhs_combine(T fp, T um, T upv, T cm, T cp, bool skm, bool skp)
+{
+    T r = fp;
+    const T tm = cm * um, tp = cp * upv;
     r -= skm ? T(0) : tm;
     r -= skp ? T(0) : tp;
     return r;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T point_rhs_rec(const Dims &d, const ChunkAddr &a, T cm, T cp,
+                                                    const T *__restrict__ ub, const T *__restrict__ fb, int k)
+{
+    const RecSlots q = rec_point_slots(d, a, k);
+    return rec_rhs_combine<T>(fb[q.p], ub[q.pm], ub[q.pp], cm, cp, q.skm, q.skp);
 }
 
 // the chunk's cross-axis coefficients (2D): toward - and + across its axis
