@@ -1078,29 +1078,27 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         const int L = ch.len;
         T tb, tf;
         chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
+        // the chunk's right-hand sides first, all reads issued together, then
+        // the elimination chain
+        T R[CH];
         if (DIM == 2) {
             // tail levels are row-major: the lane builds its chunk's record
             const ChunkAddr a = row_chunk_addr(d, ch);
             T cm, cp;
             chunk_cross_coefs<T>(cf, ch, cm, cp);
-            const T rL = point_rhs_rec<T>(d, a, cm, cp, ub, fb, L - 1) - tf - (L == 1 ? tb : T(0));
-            sweep_phase1<T, DIM, false, true>(
-                d, cf,
-                [&](int k) {
-                    const T r = point_rhs_rec<T>(d, a, cm, cp, ub, fb, k < L ? k : 0);
-                    return k == 0 ? r - tb : r;
-                },
-                rL, ch, t, red, st);
+#pragma unroll
+            for (int k = 0; k < CH; ++k) R[k] = point_rhs_rec<T>(d, a, cm, cp, ub, fb, k < L ? k : 0);
         } else {
-            const T rL = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, L - 1) - tf - (L == 1 ? tb : T(0));
-            sweep_phase1<T, DIM, false, true>(
-                d, cf,
-                [&](int k) {
-                    const T r = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
-                    return k == 0 ? r - tb : r;
-                },
-                rL, ch, t, red, st);
+#pragma unroll
+            for (int k = 0; k < CH; ++k) R[k] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
         }
+        // the last point's value, selected without indexing the array
+        T rl = R[0];
+#pragma unroll
+        for (int k = 1; k < CH; ++k) rl = (k == L - 1) ? R[k] : rl;
+        const T rL = rl - tf - (L == 1 ? tb : T(0));
+        sweep_phase1<T, DIM, false, true>(
+            d, cf, [&](int k) { return k == 0 ? R[0] - tb : R[k]; }, rL, ch, t, red, st);
     }
     __syncthreads();
     Block bk;

@@ -165,11 +165,11 @@ int find_root(std::vector<int> &par, int x)
     return x;
 }
 
-// split a straight sequence of points into chunks of at most CH points that
-// each lie in one plane of the level's layout and have at most one point per
-// side whose cross neighbour is kept in the other plane (the addressing record
-// of a 2D chunk holds one such exception per side)
-void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, HostBlock &hb)
+// split a straight sequence of points into chunks of at most maxlen (<= CH)
+// points that each lie in one plane of the level's layout and have at most
+// one point per side whose cross neighbour is kept in the other plane (the
+// addressing record of a 2D chunk holds one such exception per side)
+void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, HostBlock &hb, int maxlen)
 {
     const int n = (int)pts.size();
     const int ax = axdir >> 1, qx = ax == 0 ? 0 : 1, qy = ax == 0 ? 1 : 0;
@@ -183,7 +183,7 @@ void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, Hos
     }
     for (int s = 0; s < n;) {
         int e = s + 1, cm = om[s], cp = opp[s];
-        while (e < n && e - s < CH && pl[e] == pl[s] && cm + om[e] <= 1 && cp + opp[e] <= 1) {
+        while (e < n && e - s < maxlen && pl[e] == pl[s] && cm + om[e] <= 1 && cp + opp[e] <= 1) {
             cm += om[e];
             cp += opp[e];
             ++e;
@@ -213,8 +213,11 @@ void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, Hos
 
 // Build the block list of one motif on one level (every interior point in
 // exactly one block).  Returns MG_OK or MG_EUNSUPPORTED for shapes the
-// chunked solver does not handle.
-int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
+// chunked solver does not handle.  maxlen: the longest chunk (CH, or less
+// for the coarse-level kernel, whose lanes read their chunks' points from LDS
+// directly: chunks of CH points would put the lanes of a straight run CH
+// doubles apart, on the same LDS banks)
+int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out, int maxlen = CH)
 {
     const long long nn = g.nn;
     std::vector<long long> lab(nn, -1);
@@ -301,7 +304,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
         const long long edges = edges2 / 2;
         if (size == 1) {
             hb.type = BT_CHAIN;
-            chunk_seq(gc, {pts[b]}, 1, hb);
+            chunk_seq(gc, {pts[b]}, 1, hb, maxlen);
         } else if (edges == size - 1 && nbranch <= 1) {
             // tree: a straight line (chain), an L (spider with two legs) or a spider
             std::vector<std::vector<long long>> legs;
@@ -332,7 +335,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                     if (dirs[k] != dirs[k - 1]) turns.push_back((int)k);
                 if (turns.empty()) {
                     hb.type = BT_CHAIN;
-                    chunk_seq(gc, path, dirs[0], hb);
+                    chunk_seq(gc, path, dirs[0], hb, maxlen);
                 } else if (turns.size() == 1) {
                     const int tj = turns[0]; // path[tj] is the turning point
                     J = path[tj];
@@ -387,7 +390,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                 if (hb.m > 7) return MG_EUNSUPPORTED;
                 uint8_t jmask = 0;
                 for (int lg = 1; lg < hb.m; ++lg) {
-                    chunk_seq(gc, legs[lg], legdir[lg], hb);
+                    chunk_seq(gc, legs[lg], legdir[lg], hb, maxlen);
                     Chunk &last = hb.ch.back();
                     last.flags |= CF_NEXT | CF_NEXT_DIRECT;
                     last.nextdir = (uint8_t)legdir[lg];
@@ -397,7 +400,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
                 }
                 std::vector<long long> l0 = legs[0];
                 l0.push_back(J);
-                chunk_seq(gc, l0, legdir[0], hb);
+                chunk_seq(gc, l0, legdir[0], hb, maxlen);
                 hb.ch.back().flags |= CF_JUNCTION;
                 hb.ch.back().jmask = jmask;
             }
@@ -435,7 +438,7 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out)
             std::vector<int> firsts;
             for (size_t s = 0; s < sides.size(); ++s) {
                 firsts.push_back((int)hb.ch.size());
-                chunk_seq(gc, sides[s], sdir[s], hb);
+                chunk_seq(gc, sides[s], sdir[s], hb, maxlen);
                 Chunk &last = hb.ch.back();
                 last.flags |= CF_NEXT;
                 last.nextdir = (uint8_t)sdir[(s + 1) % sides.size()];
@@ -1211,8 +1214,13 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         Level &L = h->lev[l];
         for (int s = 0; s < 2; ++s) {
             if (h->slot_motif[s] < 0) continue;
+            // levels small enough for the coarse-level kernel: chunks of
+            // CH - 1 points (its lanes read their chunks' points from LDS
+            // directly, where chunks of CH points would put the lanes of a
+            // straight run on the same banks)
+            const bool tail_size = L.d.nn * 2 * (long long)sizeof(double) <= TAIL_BYTES;
             std::vector<HostBlock> blocks;
-            rc = build_blocks(L.g, h->slot_motif[s], blocks);
+            rc = build_blocks(L.g, h->slot_motif[s], blocks, tail_size ? CH - 1 : CH);
             if (rc) return rc;
             for (int colour = 0; colour < 2; ++colour) {
                 std::vector<const HostBlock *> sel;
@@ -1221,8 +1229,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 HostTable &t = L.htab[s][colour];
                 // narrow workgroups for 2D levels too large for the
                 // coarse-level kernel (whose sweeps use NT/2 lanes)
-                const bool narrow = dim == 2 && L.d.nn * 2 * (long long)sizeof(double) > TAIL_BYTES &&
-                                    !std::getenv("TWMG_WIDE_WG");
+                const bool narrow = dim == 2 && !tail_size && !std::getenv("TWMG_WIDE_WG");
                 pack(sel, t, narrow);
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;
