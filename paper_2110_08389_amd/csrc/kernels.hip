@@ -823,18 +823,53 @@ __device__ __forceinline__ bool in_col(const Dims &d, int i, int j)
     return d.layout != LAYOUT_ROW && col_plane(d, i, j);
 }
 
-// rectangle [ia, ia + W) x [ja, ja + H) of a (layout d) -> t[y * P + x];
-// nodes outside the grid read as 0.  jfast: thread order with j fastest.
-template <typename T, int W, int H, int P>
-__device__ __forceinline__ void load_rect(const Dims &d, const T *__restrict__ a, int ia, int ja, bool jfast, T *t)
-{
-    for (int q = threadIdx.x; q < W * H; q += blockDim.x) {
-        const int x = jfast ? q / H : q % W, y = jfast ? q % H : q / W;
-        const int i = ia + x, j = ja + y;
-        T v = 0;
-        if (i >= 0 && i <= d.n[0] && j >= 0 && j <= d.n[1]) v = a[nidx(d, i, j, 0)];
-        t[y * P + x] = v;
+// A node rectangle read by a 256-lane workgroup in two steps: load() issues
+// every read of the thread's share (fixed count, indices clamped into the grid
+// and the values outside it zeroed, so that no branch separates the reads),
+// store() puts them into LDS (row pitch P).  Consecutive threads take
+// consecutive nodes along the fast axis of the plane holding the rectangle.
+template <typename T, int W, int H> struct RectBuf {
+    static constexpr int NQ = (W * H + 255) / 256;
+    T v[NQ];
+    __device__ __forceinline__ void load(const Dims &d, const T *__restrict__ a, int ia, int ja, bool jfast)
+    {
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = threadIdx.x + 256 * r;
+            const int x = jfast ? q / H : q % W, y = jfast ? q % H : q / W;
+            const int i = ia + x, j = ja + y;
+            const bool ok = q < W * H && i >= 0 && i <= d.n[0] && j >= 0 && j <= d.n[1];
+            const int ic = min(max(i, 0), d.n[0]), jc = min(max(j, 0), d.n[1]);
+            const T val = a[nidx(d, ic, jc, 0)];
+            v[r] = ok ? val : T(0);
+        }
     }
+    __device__ __forceinline__ void store(T *t, int P, bool jfast) const
+    {
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = threadIdx.x + 256 * r;
+            const int x = jfast ? q / H : q % W, y = jfast ? q % H : q / W;
+            if (q < W * H) t[y * P + x] = v[r];
+        }
+    }
+};
+
+// The coefficients along a tile's two axes, for nodes ia .. ia+W-1 along x
+// and ja .. ja+W-1 along y (clamped into the arrays; entries past the grid are
+// never used): s[0..2][x] = lo_x, hi_x, dg_x; s[3..5][y] = lo_y, hi_y, dg_y.
+// One read per thread (6 W <= 256).
+template <typename T, int W>
+__device__ __forceinline__ T tile_coef_load(const Dims &d, const Coef<T> &cf, int ia, int ja)
+{
+    const int q = threadIdx.x, a = q / W, k = q % W;
+    if (q >= 6 * W) return T(0);
+    const int ax = a / 3, kind = a % 3;
+    const int idx = min(max((ax ? ja : ia) + k, 0), ax ? d.n[1] : d.n[0]);
+    // the block's arrays by offset (an index into the pointer arrays would be
+    // a read of a private copy of the descriptor)
+    const int arr = kind == 2 ? 6 + ax : 2 * ax + kind;
+    return cf.base[arr * cf.cs + idx];
 }
 
 // fused defect + full weighting, 16 x 16 coarse interior nodes per workgroup:
@@ -855,21 +890,35 @@ __global__ void __launch_bounds__(256) k_restrict_tile(Dims fd, Dims cd, Coef<T>
     const T *ub = u + (long long)blockIdx.y * fd.bs;
     const T *fb = f + (long long)blockIdx.y * fd.bs;
     const bool jf = in_col(fd, fi + CT, fj + CT);
-    load_rect<T, UW, UW, UW>(fd, ub, fi - 1, fj - 1, jf, su);
-    load_rect<T, FW, FW, FW>(fd, fb, fi, fj, jf, sd);
+    __shared__ T sc[6 * FW];
+    {
+        // every read of the workgroup issued before any is stored
+        RectBuf<T, UW, UW> ru;
+        RectBuf<T, FW, FW> rf;
+        ru.load(fd, ub, fi - 1, fj - 1, jf);
+        rf.load(fd, fb, fi, fj, jf);
+        const T cv = tile_coef_load<T, FW>(fd, cf, fi, fj);
+        __builtin_amdgcn_sched_barrier(0);
+        ru.store(su, UW, jf);
+        rf.store(sd, FW, jf);
+        if (threadIdx.x < 6 * FW) sc[threadIdx.x] = cv;
+    }
     __syncthreads();
-    for (int q = threadIdx.x; q < FW * FW; q += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < (FW * FW + 255) / 256; ++r) {
+        const int q = threadIdx.x + 256 * r;
+        if (q >= FW * FW) break;
         const int x = jf ? q / FW : q % FW, y = jf ? q % FW : q / FW;
         const int i = fi + x, j = fj + y;
-        T r = 0;
+        T rd = 0;
         if (i > 0 && i < fd.n[0] && j > 0 && j < fd.n[1]) {
             const T *c = &su[(y + 1) * UW + (x + 1)];
-            T sum = cf.lo[0][i] * c[-1] + cf.hi[0][i] * c[1];
-            sum += cf.lo[1][j] * c[-UW] + cf.hi[1][j] * c[UW];
-            const T dg = cf.dg[0][i] + cf.dg[1][j];
-            r = sd[y * FW + x] - (sum + dg * c[0]);
+            T sum = sc[x] * c[-1] + sc[FW + x] * c[1];
+            sum += sc[3 * FW + y] * c[-UW] + sc[4 * FW + y] * c[UW];
+            const T dg = sc[2 * FW + x] + sc[5 * FW + y];
+            rd = sd[y * FW + x] - (sum + dg * c[0]);
         }
-        sd[y * FW + x] = r;
+        sd[y * FW + x] = rd;
     }
     __syncthreads();
     const T w3[3] = {T(0.25), T(0.5), T(0.25)};
@@ -906,19 +955,40 @@ __global__ void __launch_bounds__(256) k_prolong_tile(Dims fd, Dims cd, const T 
     T *ub = u + (long long)blockIdx.y * fd.bs;
     const T *eb = ec + (long long)blockIdx.y * cd.bs;
     const bool jf = in_col(fd, i0 + FT / 2, j0 + FT / 2);
-    load_rect<T, CW, CW, CW>(cd, eb, i0 / 2, j0 / 2, jf, se);
+    // the fine values this thread updates are read together with the coarse
+    // rectangle
+    constexpr int NQ = FT * FT / 256;
+    T uf[NQ];
+    long long pf[NQ];
+    bool okf[NQ];
+    {
+        RectBuf<T, CW, CW> re;
+        re.load(cd, eb, i0 / 2, j0 / 2, jf);
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = threadIdx.x + 256 * r;
+            const int x = jf ? q / FT : q % FT, y = jf ? q % FT : q / FT;
+            const int i = i0 + x, j = j0 + y;
+            okf[r] = i > 0 && i < fd.n[0] && j > 0 && j < fd.n[1];
+            pf[r] = nidx(fd, min(i, fd.n[0]), min(j, fd.n[1]), 0);
+            uf[r] = ub[pf[r]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        re.store(se, CW, jf);
+    }
     __syncthreads();
-    for (int q = threadIdx.x; q < FT * FT; q += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const int q = threadIdx.x + 256 * r;
         const int x = jf ? q / FT : q % FT, y = jf ? q % FT : q / FT;
         const int i = i0 + x, j = j0 + y;
-        if (i <= 0 || i >= fd.n[0] || j <= 0 || j >= fd.n[1]) continue;
         // coarse neighbours in the rectangle: (I - i0/2, J - j0/2)
         const int X0 = (i >> 1) - i0 / 2, X1 = ((i + 1) >> 1) - i0 / 2;
         const int Y0 = (j >> 1) - j0 / 2, Y1 = ((j + 1) >> 1) - j0 / 2;
         const T r0 = (X0 == X1) ? se[Y0 * CW + X0] : T(0.5) * (se[Y0 * CW + X0] + se[Y0 * CW + X1]);
         const T r1 = (X0 == X1) ? se[Y1 * CW + X0] : T(0.5) * (se[Y1 * CW + X0] + se[Y1 * CW + X1]);
         const T v = (Y0 == Y1) ? r0 : T(0.5) * (r0 + r1);
-        ub[nidx(fd, i, j, 0)] += v;
+        if (okf[r]) ub[pf[r]] = uf[r] + v;
     }
 }
 
@@ -1272,6 +1342,7 @@ __global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const 
 {
     constexpr int TS = 32, UW = TS + 2;
     __shared__ T su[UW * UW];
+    __shared__ T sc[6 * TS];
     const long long boff = (long long)blockIdx.y * d.bs;
     const int tx = (d.n[0] + TS) / TS, ty = (d.n[1] + TS) / TS;
     double m = 0.0;
@@ -1281,23 +1352,41 @@ __global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const 
         const int i0 = (tile % tx) * TS, j0 = (tile / tx) * TS;
         const bool jf = in_col(d, i0 + TS / 2, j0 + TS / 2);
         __syncthreads();
-        load_rect<T, UW, UW, UW>(d, u + boff, i0 - 1, j0 - 1, jf, su);
+        // every read of the tile issued before any is used: u with its halo,
+        // the thread's f values, the coefficient strips
+        constexpr int NQ = TS * TS / 256;
+        T fv[NQ];
+        {
+            RectBuf<T, UW, UW> ru;
+            ru.load(d, u + boff, i0 - 1, j0 - 1, jf);
+#pragma unroll
+            for (int r = 0; r < NQ; ++r) {
+                const int q = threadIdx.x + 256 * r;
+                const int x = jf ? q / TS : q % TS, y = jf ? q % TS : q / TS;
+                fv[r] = f[boff + nidx(d, min(i0 + x, d.n[0]), min(j0 + y, d.n[1]), 0)];
+            }
+            const T cv = tile_coef_load<T, TS>(d, cf, i0, j0);
+            __builtin_amdgcn_sched_barrier(0);
+            ru.store(su, UW, jf);
+            if (threadIdx.x < 6 * TS) sc[threadIdx.x] = cv;
+        }
         __syncthreads();
-        for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = threadIdx.x + 256 * r;
             const int x = jf ? q / TS : q % TS, y = jf ? q % TS : q / TS;
             const int i = i0 + x, j = j0 + y;
             if (i > d.n[0] || j > d.n[1]) continue;
-            const long long p = boff + nidx(d, i, j, 0);
-            T r = 0;
+            T rd = 0;
             if (i > 0 && i < d.n[0] && j > 0 && j < d.n[1]) {
                 const T *c = &su[(y + 1) * UW + (x + 1)];
-                T sum = cf.lo[0][i] * c[-1] + cf.hi[0][i] * c[1];
-                sum += cf.lo[1][j] * c[-UW] + cf.hi[1][j] * c[UW];
-                const T dg = cf.dg[0][i] + cf.dg[1][j];
-                r = f[p] - (sum + dg * c[0]);
+                T sum = sc[x] * c[-1] + sc[TS + x] * c[1];
+                sum += sc[3 * TS + y] * c[-UW] + sc[4 * TS + y] * c[UW];
+                const T dg = sc[2 * TS + x] + sc[5 * TS + y];
+                rd = fv[r] - (sum + dg * c[0]);
             }
-            if (TO32) r32[p] = (float)r;
-            const double a = fabs((double)r);
+            if (TO32) r32[boff + nidx(d, i, j, 0)] = (float)rd;
+            const double a = fabs((double)rd);
             nan = nan || (a != a);
             m = fmax(m, a);
         }
