@@ -212,28 +212,34 @@ __host__ __device__ __forceinline__ void chunk_end_terms(const Dims &d, const Co
     const int cax0 = ax == 0 ? i0 : (ax == 1 ? j0 : l0), caxL = cax0 + (L - 1) * sg;
     const bool boff = !((inblock_dirs(ch, 0) >> (ad ^ 1)) & 1u);
     const bool foff = !((inblock_dirs(ch, L - 1) >> ad) & 1u);
-    // the neighbours exist (the end points are interior); in-block ones are
-    // read too and dropped by the select
-    const T ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
-    const T ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
+    // only neighbours outside the block are read (an in-block neighbour is a
+    // point of the colour being relaxed, whose cache lines are otherwise only
+    // written)
+    T ubk = 0, ufw = 0;
+    if (boff) ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
+    if (foff) ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
     tb = boff ? coef_arr_rt<T, DIM>(cf, ad ^ 1)[cax0] * ubk : T(0);
     tf = foff ? coef_arr_rt<T, DIM>(cf, ad)[caxL] * ufw : T(0);
 }
 
-// The chunk's two outside neighbours along its axis: ubk before the first
-// point, ufw after the last (their couplings are dropped by chunk_end_terms_v
-// when the neighbour is in the block).
+// The chunk's two neighbours along its axis: ubk before the first point, ufw
+// after the last, each read only when it lies outside the block (otherwise 0;
+// chunk_end_terms_v drops its coupling).
 template <typename T, int DIM>
 __host__ __device__ __forceinline__ void chunk_end_u(const Dims &d, const T *__restrict__ ub, const Chunk &ch, T &ubk,
                                                      T &ufw)
 {
-    const int L = ch.len, ax = ch.axdir >> 1;
-    const int sg = (ch.axdir & 1) ? 1 : -1;
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
     const int e[3] = {ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0};
     const int i0 = ch.c0[0], j0 = ch.c0[1], l0 = DIM == 3 ? ch.c0[2] : 0;
     const int iL = i0 + (L - 1) * e[0], jL = j0 + (L - 1) * e[1], lL = l0 + (L - 1) * e[2];
-    ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
-    ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
+    const bool boff = !((inblock_dirs(ch, 0) >> (ad ^ 1)) & 1u);
+    const bool foff = !((inblock_dirs(ch, L - 1) >> ad) & 1u);
+    ubk = 0;
+    ufw = 0;
+    if (boff) ubk = ub[slot32(d, i0 - e[0], j0 - e[1], DIM == 3 ? l0 - e[2] : 0)];
+    if (foff) ufw = ub[slot32(d, iL + e[0], jL + e[1], DIM == 3 ? lL + e[2] : 0)];
 }
 
 // chunk_end_terms from the loaded neighbours and the two coefficients: ab, the
