@@ -494,7 +494,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             chunk_end_terms_v<T>(chl, Av[0], cLf, ubk, ufw, tb, tf);
             const T *rp = &s_pt[t * PS];
             const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
-            sweep_phase1_coefs<T, DIM, false, true, DOFF>(
+            sweep_phase1_coefs<T, DIM, false, true, DOFF, CH>(
                 d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st, Av, Cv, Bv, aL,
                 bLax, sc);
         }
@@ -1126,7 +1126,8 @@ hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f
 // Block sweep of one workgroup descriptor with u, f, coefficients and tables
 // in LDS: each lane forms its chunk's right-hand sides directly (no staging),
 // phases 1-3 as in the main sweep, new values written in place.
-template <typename T, int DIM>
+// C: the longest chunk of the level (the code runs over C positions per lane)
+template <typename T, int DIM, int C>
 __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, T *ub, const T *fb,
                                               const Chunk *chunks, const Block *blocks, const WGDesc w,
                                               const NodeFac<T> *fac, int rings, T *s_rs, T *s_rn, T *s_dl, T *s_x,
@@ -1135,7 +1136,7 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
     const int t = threadIdx.x;
     const bool act = t < w.nchunk;
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
-    LaneState<T> st;
+    LaneState<T, C> st;
     uint8_t nfl = 0;
     int ext = -1;
     NodeFac<T> nf{0, 0, 0, 0};
@@ -1150,24 +1151,24 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         chunk_end_terms<T, DIM>(d, cf, ub, ch, tb, tf);
         // the chunk's right-hand sides first, all reads issued together, then
         // the elimination chain
-        T R[CH];
+        T R[C];
         if (DIM == 2) {
             // tail levels are row-major: the lane builds its chunk's record
             const ChunkAddr a = row_chunk_addr(d, ch);
             T cm, cp;
             chunk_cross_coefs<T>(cf, ch, cm, cp);
 #pragma unroll
-            for (int k = 0; k < CH; ++k) R[k] = point_rhs_rec<T>(d, a, cm, cp, ub, fb, k < L ? k : 0);
+            for (int k = 0; k < C; ++k) R[k] = point_rhs_rec<T>(d, a, cm, cp, ub, fb, k < L ? k : 0);
         } else {
 #pragma unroll
-            for (int k = 0; k < CH; ++k) R[k] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
+            for (int k = 0; k < C; ++k) R[k] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, k < L ? k : 0);
         }
         // the last point's value, selected without indexing the array
         T rl = R[0];
 #pragma unroll
-        for (int k = 1; k < CH; ++k) rl = (k == L - 1) ? R[k] : rl;
+        for (int k = 1; k < C; ++k) rl = (k == L - 1) ? R[k] : rl;
         const T rL = rl - tf - (L == 1 ? tb : T(0));
-        sweep_phase1<T, DIM, false, true>(
+        sweep_phase1<T, DIM, false, true, false, C>(
             d, cf, [&](int k) { return k == 0 ? R[0] - tb : R[k]; }, rL, ch, t, red, st);
     }
     __syncthreads();
@@ -1179,9 +1180,9 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
     if (act) {
         if (DIM == 2) {
             const ChunkAddr a = row_chunk_addr(d, ch);
-            sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[rec_slot(d, a, k)] = v; });
+            sweep_phase3_each<T, C>(t, red, st, [&](int k, T v) { ub[rec_slot(d, a, k)] = v; });
         } else {
-            sweep_phase3_each<T>(t, red, st, [&](int k, T v) { ub[point_index(d, ch, k)] = v; });
+            sweep_phase3_each<T, C>(t, red, st, [&](int k, T v) { ub[point_index(d, ch, k)] = v; });
         }
     }
 }
@@ -1227,8 +1228,12 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
             const WGDesc *wgs = reinterpret_cast<const WGDesc *>(s_mem + L.wg_off[sl][c]);
             const NodeFac<T> *fac = reinterpret_cast<const NodeFac<T> *>(s_mem + L.fac_off[sl][c]);
             for (int w = 0; w < nw; ++w) {
-                sweep_wg_tail<T, DIM>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c], s_rs, s_rn, s_dl,
-                                      s_x, s_a, s_b);
+                if (L.short_chunks)
+                    sweep_wg_tail<T, DIM, TAIL_SHORT_CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c],
+                                                         s_rs, s_rn, s_dl, s_x, s_a, s_b);
+                else
+                    sweep_wg_tail<T, DIM, CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c], s_rs, s_rn,
+                                              s_dl, s_x, s_a, s_b);
                 __syncthreads();
             }
         } else if (op.kind == TO_CHECKER) {

@@ -80,8 +80,10 @@ template <typename T> struct RedArrays {
     T *aux;  // coupling of the successor node's row back to q (branch rows)
 };
 
-template <typename T> struct LaneState {
-    T D[CH], G[CH], S[CH]; // interior elimination: delta, gamma, left spike
+// C: the longest chunk the lane may own (CH, or fewer in code compiled for
+// short chunks)
+template <typename T, int C = CH> struct LaneState {
+    T D[C], G[C], S[C]; // interior elimination: delta, gamma, left spike
     int L, prev;
     bool hp;
 };
@@ -389,12 +391,12 @@ __host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &
 // DATA: build the right-hand-side part (reads u, f); MATRIX: build the
 // geometry-only reduced matrix (low, ds, dn, up, aux), used at setup to factor
 // the reduced systems once.  The kernel runs DATA only.
-// rr(k) returns the right-hand side of point k (point_rhs) for k < CH - 1; it
+// rr(k) returns the right-hand side of point k (point_rhs) for k < C - 1; it
 // is called once per k, in increasing order, so it may compute the value on
 // the spot.  rL is the right-hand side of the last point (index len - 1).
 // The along-axis coefficients come in as values: Av[k] toward the predecessor
 // point, Cv[k] toward the successor and Bv[k] the along-axis part of the
-// diagonal, for k < CH (entries from len - 1 on are computed with but never
+// diagonal, for k < C (entries from len - 1 on are computed with but never
 // used); aL and bLax are those of the last point.
 // DIAG_FROM_OFF: the along-axis part of the diagonal is -(a + c) (Bv unused);
 // valid for the FP64 forward operator, whose stored diagonal arrays are
@@ -430,10 +432,10 @@ __host__ __device__ __forceinline__ ChunkScalars<T> chunk_scalars(const Coef<T> 
     return r;
 }
 
-template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF, typename RR>
+template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF, int C, typename RR>
 __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
                                                             const Chunk &ch, int t, const RedArrays<T> &s,
-                                                            LaneState<T> &st, const T *Av, const T *Cv,
+                                                            LaneState<T, C> &st, const T *Av, const T *Cv,
                                                             const T *Bv, T aL, T bLax, const ChunkScalars<T> &sc)
 {
     const int L = ch.len;
@@ -462,10 +464,10 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
         s.aux[t] = coef_arr_rt<T, DIM>(cf, nx ^ 1)[cn + ns];
     }
     // elimination of the interior (points 0..L-2) with zero end values; run
-    // branch-free over all CH positions, entries from L-1 on are not used
+    // branch-free over all C positions, entries from L-1 on are not used
     T Gp = 0, Dp = 0, Sp = hp ? T(1) : T(0);
 #pragma unroll
-    for (int k = 0; k < CH - 1; ++k) {
+    for (int k = 0; k < C - 1; ++k) {
         const T r = DATA ? rr(k) : T(0);
         const T bk = DIAG_FROM_OFF ? -(Av[k] + Cv[k]) : Bv[k];
         const T b = (ax == 0) ? bk + bfix : bfix + bk;
@@ -481,7 +483,7 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
     // first-point values of the zero-end interior solution y and its spikes v, w
     T yl = 0, vl = 0, wl = 0, y = 0, v = 0, ww = 0;
 #pragma unroll
-    for (int k = CH - 2; k >= 0; --k) {
+    for (int k = C - 2; k >= 0; --k) {
         const bool last = (k == L - 2), in = (k < L - 2);
         y = last ? st.D[k] : (in ? st.D[k] - st.G[k] * y : y);
         yl = last ? y : yl;
@@ -519,10 +521,10 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
 
 // Phase 1 loading the chunk's along-axis coefficients itself (one lane per
 // chunk), all before the elimination chain so that their latency is paid once.
-template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF = false, typename RR>
+template <typename T, int DIM, bool MATRIX, bool DATA, bool DIAG_FROM_OFF = false, int C = CH, typename RR>
 __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<T> &cf, RR &&rr, T rL,
                                                       const Chunk &ch, int t, const RedArrays<T> &s,
-                                                      LaneState<T> &st)
+                                                      LaneState<T, C> &st)
 {
     const int L = ch.len;
     const int ad = ch.axdir, ax = ad >> 1;
@@ -531,16 +533,16 @@ __host__ __device__ __forceinline__ void sweep_phase1(const Dims &d, const Coef<
     const T *Pback = coef_arr_rt<T, DIM>(cf, ad ^ 1);
     const T *Pfwd = coef_arr_rt<T, DIM>(cf, ad);
     const T *Pdg = dg_arr_rt<T>(cf, ax);
-    T Av[CH], Cv[CH], Bv[CH];
+    T Av[C], Cv[C], Bv[C];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
+    for (int k = 0; k < C; ++k) {
         const int ca = (k < L) ? cax + k * sg : cax; // clamped: stays inside the arrays
         Av[k] = Pback[ca];
         Cv[k] = Pfwd[ca];
         Bv[k] = DIAG_FROM_OFF ? T(0) : Pdg[ca];
     }
     const int cL_ = cax + (L - 1) * sg;
-    sweep_phase1_coefs<T, DIM, MATRIX, DATA, DIAG_FROM_OFF>(d, cf, rr, rL, ch, t, s, st, Av, Cv, Bv, Pback[cL_],
+    sweep_phase1_coefs<T, DIM, MATRIX, DATA, DIAG_FROM_OFF, C>(d, cf, rr, rL, ch, t, s, st, Av, Cv, Bv, Pback[cL_],
                                                              Pdg[cL_], chunk_scalars<T, DIM>(cf, ch));
 }
 
@@ -591,15 +593,15 @@ __host__ void reduced_solve_seq(int n, const Chunk *ch, const NodeFac<T> *fac, c
 
 // Phase 3 with a store callback: put(k, x_k) for k = 0 .. len-1 (used where u
 // is written in place, as in the coarse-level kernel).
-template <typename T, typename F>
-__host__ __device__ __forceinline__ void sweep_phase3_each(int t, const RedArrays<T> &s, const LaneState<T> &st,
+template <typename T, int C = CH, typename F>
+__host__ __device__ __forceinline__ void sweep_phase3_each(int t, const RedArrays<T> &s, const LaneState<T, C> &st,
                                                            F &&put)
 {
     const T Xp = st.hp ? s.x[st.prev] : T(0);
     const T Xo = s.x[t];
     T x = Xo;
 #pragma unroll
-    for (int k = CH - 2; k >= 0; --k) {
+    for (int k = C - 2; k >= 0; --k) {
         const T xn = st.D[k] + st.S[k] * Xp - st.G[k] * x;
         x = (k <= st.L - 2) ? xn : x;
         if (k <= st.L - 2) put(k, x);
@@ -609,9 +611,9 @@ __host__ __device__ __forceinline__ void sweep_phase3_each(int t, const RedArray
 
 // Phase 3: back-substitution of the chunk interior from the node values;
 // xx[k] receives the new value of point k (the caller scatters it to u).
-template <typename T>
+template <typename T, int C = CH>
 __host__ __device__ __forceinline__ void sweep_phase3(T *__restrict__ xx, int t, const RedArrays<T> &s,
-                                                      const LaneState<T> &st)
+                                                      const LaneState<T, C> &st)
 {
     const T Xp = st.hp ? s.x[st.prev] : T(0);
     const T Xo = s.x[t];
@@ -619,7 +621,7 @@ __host__ __device__ __forceinline__ void sweep_phase3(T *__restrict__ xx, int t,
     // branch-free: positions past the interior keep x = Xo; entries k >= L of
     // xx are scratch and never scattered
 #pragma unroll
-    for (int k = CH - 2; k >= 0; --k) {
+    for (int k = C - 2; k >= 0; --k) {
         const T xn = st.D[k] + st.S[k] * Xp - st.G[k] * x;
         x = (k <= st.L - 2) ? xn : x;
         xx[k] = x;

@@ -1007,6 +1007,12 @@ size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char
             t.cs = (int)L.cs;
         }
         if (lt + r == h->nlev - 1) continue;
+        t.short_chunks = 1;
+        for (int sl = 0; sl < 2; ++sl)
+            for (int c = 0; c < 2; ++c)
+                if (h->slot_motif[sl] >= 0)
+                    for (const Chunk &ch : L.htab[sl][c].chunks)
+                        if (ch.len > TAIL_SHORT_CH) t.short_chunks = 0;
         for (int sl = 0; sl < 2; ++sl)
             for (int c = 0; c < 2; ++c) {
                 if (h->slot_motif[sl] < 0) continue;
@@ -1218,9 +1224,13 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             // CH - 1 points (its lanes read their chunks' points from LDS
             // directly, where chunks of CH points would put the lanes of a
             // straight run on the same banks)
+            // (and TAIL_SHORT_CH points on the smallest of them)
             const bool tail_size = L.d.nn * 2 * (long long)sizeof(double) <= TAIL_BYTES;
+            int nmax = 0;
+            for (int a = 0; a < dim; ++a) nmax = std::max(nmax, L.d.n[a]);
+            const int maxlen = !tail_size ? CH : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
             std::vector<HostBlock> blocks;
-            rc = build_blocks(L.g, h->slot_motif[s], blocks, tail_size ? CH - 1 : CH);
+            rc = build_blocks(L.g, h->slot_motif[s], blocks, maxlen);
             if (rc) return rc;
             for (int colour = 0; colour < 2; ++colour) {
                 std::vector<const HostBlock *> sel;

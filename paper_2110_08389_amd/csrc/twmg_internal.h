@@ -189,6 +189,11 @@ struct SweepTable {
 // kernel copies into LDS; all offsets below are byte offsets into LDS.
 constexpr int TAIL_BYTES = 147456; // LDS bytes for the image plus the levels' u, f and solve scratch
 constexpr int TAIL_NT = NT / 2;    // lanes of the coarse-level workgroup
+// chunk length on the smallest levels of the coarse-level kernel: its sweeps
+// are bound by one workgroup's instruction issue, which a lane's chunk length
+// sets (code for C positions runs whatever the actual length)
+constexpr int TAIL_SHORT_CH = 4;
+constexpr int TAIL_SHORT_MAXN = 32; // levels with at most this many cells per axis
 
 enum TailOpKind : uint8_t { TO_SWEEP = 0, TO_CHECKER = 1, TO_RESTRICT = 2, TO_PROLONG = 3, TO_SOLVE = 4 };
 struct TailOp {
@@ -206,6 +211,7 @@ struct TailLevel {
     int chunk_off[2][2], block_off[2][2], wg_off[2][2], fac_off[2][2]; // [slot][colour] block tables
     int nwg[2][2];
     int rings[2][2];
+    int short_chunks;  // every chunk of the level has at most TAIL_SHORT_CH points
 };
 
 template <typename T> struct TailPlan {
