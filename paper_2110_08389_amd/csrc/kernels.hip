@@ -338,22 +338,22 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The along-axis coefficients of a chunk's CH positions from one coefficient
+// The along-axis coefficients of a chunk's C positions from one coefficient
 // array P (out[k] at position cax + k for up, cax - k otherwise; entries from
 // the chunk's length on are values of neighbouring positions and go unused).
-// The CH-position window is read as CH/2 + 1 aligned pairs: the arrays start
-// at even offsets from a 16-byte aligned block with CH + 2 spare entries
+// The C-position window is read as C/2 + 1 aligned pairs: the arrays start
+// at even offsets from a 16-byte aligned block with CH + 2 >= C + 2 spare entries
 // before and after it, so every window stays inside the allocation.
-template <typename T>
-__device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int cax, int up, T (&out)[CH])
+template <typename T, int C>
+__device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int cax, int up, T (&out)[C])
 {
     typedef T V2 __attribute__((ext_vector_type(2)));
-    const int lo = up ? cax : cax - (CH - 1);
+    const int lo = up ? cax : cax - (C - 1);
     const int e0 = lo & ~1, off = lo - e0;
     const V2 *p2 = reinterpret_cast<const V2 *>(P + e0);
-    T W[CH + 2];
+    T W[C + 2];
 #pragma unroll
-    for (int q = 0; q < CH / 2 + 1; ++q) {
+    for (int q = 0; q < C / 2 + 1; ++q) {
         const V2 v = p2[q];
         W[2 * q] = v.x;
         W[2 * q + 1] = v.y;
@@ -365,9 +365,9 @@ __device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int c
     const U mo = off ? ~U(0) : U(0), mu = up ? ~U(0) : U(0);
     auto bits = [](T v) { return __builtin_bit_cast(U, v); };
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
+    for (int k = 0; k < C; ++k) {
         const U a = (bits(W[k]) & ~mo) | (bits(W[k + 1]) & mo);
-        const U b = (bits(W[CH - 1 - k]) & ~mo) | (bits(W[CH - k]) & mo);
+        const U b = (bits(W[C - 1 - k]) & ~mo) | (bits(W[C - k]) & mo);
         out[k] = __builtin_bit_cast(T, (b & ~mu) | (a & mu));
     }
 }
@@ -379,14 +379,19 @@ __device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int c
 // which reach the lanes that own the chunks through the wavefront's rows of
 // the staging buffer; otherwise in general form, each lane loading its
 // chunk's coefficients itself.
-template <typename T, int DIM, int NT, bool DOFF, bool REC>
+// C: the chunk capacity (CH, or fewer for the small levels' short chunks;
+// records path only).
+template <typename T, int DIM, int NT, bool DOFF, bool REC, int C = CH>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
                                          const ChunkAddr *__restrict__ addrs, const T *__restrict__ cross,
                                          const Block *__restrict__ blocks, const WGDesc w,
                                          const NodeFac<T> *__restrict__ fac, int rings)
 {
-    constexpr int PS = CH + 1; // padded row of the point staging buffer (bank-conflict free)
+    static_assert(REC || C == CH, "short chunks only on the records path");
+    static_assert(64 % C == 0 && C <= CH, "chunk capacity");
+    constexpr int PS = C + 1; // padded row of the point staging buffer (bank-conflict free)
+    constexpr int CPS = 64 / C; // a wavefront's chunks per gather step
     __shared__ T s_pt[NT * PS + 1];
     // chunk descriptors (general) or addressing records and along-axis start
     // coordinates (REC)
@@ -420,7 +425,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         wave_sync();
     else
         __syncthreads();
-    LaneState<T> st;
+    LaneState<T, C> st;
     uint8_t nfl = 0;
     int ext = -1;
     // the lane's node factors and (lanes t < nblock) block t, for phase 2;
@@ -430,24 +435,25 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     bkl.type = BT_CHAIN;
     if constexpr (REC) {
         // wavefront-local gather of the right-hand sides (f minus the
-        // off-block cross couplings): in step m, lane l takes point l % CH of
-        // the wavefront's chunk 4 m + l / CH (64 consecutive points per load)
+        // off-block cross couplings): in step m, lane l takes point l % C of
+        // the wavefront's chunk (64 / C) m + l / C (64 consecutive points per
+        // load)
         // and stores it in the chunk's row of s_pt.  Positions past a chunk's
         // end repeat its first point; chunks past the workgroup's end read the
         // wavefront's first chunk and land in the spare entry.  Two batches,
         // each issuing all its loads before storing.
         const int lane = t & 63, c0w = t & ~63;
-        constexpr int GB = 8;
+        constexpr int GB = C < 8 ? C : 8;
         if (c0w < w.nchunk) {
 #pragma unroll
-            for (int m0 = 0; m0 < CH; m0 += GB) {
+            for (int m0 = 0; m0 < C; m0 += GB) {
                 // all of a batch's loads are issued before any is used
                 T fv[GB], um[GB], upv[GB], cm[GB], cp[GB];
                 bool skm[GB], skp[GB];
                 int dst[GB];
 #pragma unroll
                 for (int m = 0; m < GB; ++m) {
-                    const int c = c0w + 4 * (m0 + m) + (lane >> 4), k = lane & (CH - 1);
+                    const int c = c0w + CPS * (m0 + m) + lane / C, k = lane % C;
                     const bool inc = c < w.nchunk;
                     const int cc = inc ? c : c0w;
                     const ChunkAddr a = s_ca[cc];
@@ -482,19 +488,19 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             // neighbours outside it along its axis and its scalar coefficients
             const int ad = chl.axdir, ax = ad >> 1, up = ad & 1, L = chl.len;
             const int cax = ax ? chl.c0[1] : chl.c0[0], cL_ = cax + (up ? L - 1 : 1 - L);
-            T Av[CH], Cv[CH], Bv[CH], ubk, ufw;
+            T Av[C], Cv[C], Bv[C], ubk, ufw;
             const T aL = cf.base[(ad ^ 1) * cf.cs + cL_], bLax = cf.base[(6 + ax) * cf.cs + cL_];
             const T cLf = cf.base[ad * cf.cs + cL_];
             chunk_end_u<T, DIM>(d, ub, chl, ubk, ufw);
             const ChunkScalars<T> sc = chunk_scalars<T, DIM>(cf, chl);
-            chunk_coef_window<T>(cf.base + (ad ^ 1) * cf.cs, cax, up, Av);
-            chunk_coef_window<T>(cf.base + ad * cf.cs, cax, up, Cv);
-            if (!DOFF) chunk_coef_window<T>(cf.base + (6 + ax) * cf.cs, cax, up, Bv);
+            chunk_coef_window<T, C>(cf.base + (ad ^ 1) * cf.cs, cax, up, Av);
+            chunk_coef_window<T, C>(cf.base + ad * cf.cs, cax, up, Cv);
+            if (!DOFF) chunk_coef_window<T, C>(cf.base + (6 + ax) * cf.cs, cax, up, Bv);
             T tb, tf;
             chunk_end_terms_v<T>(chl, Av[0], cLf, ubk, ufw, tb, tf);
             const T *rp = &s_pt[t * PS];
             const T rL = rp[L - 1] - tf - (L == 1 ? tb : T(0));
-            sweep_phase1_coefs<T, DIM, false, true, DOFF, CH>(
+            sweep_phase1_coefs<T, DIM, false, true, DOFF, C>(
                 d, cf, [&](int k) { return k == 0 ? rp[0] - tb : rp[k]; }, rL, chl, t, red, st, Av, Cv, Bv, aL,
                 bLax, sc);
         }
@@ -540,7 +546,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     // the staging buffer is free until phase 3: it carries the node factors
     reduced_solve_wg<T>(w, act, nfl, ext, nf, bkl, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b, s_pt);
     __syncthreads();
-    if (act) sweep_phase3<T>(&s_pt[t * PS], t, red, st);
+    if (act) sweep_phase3<T, C>(&s_pt[t * PS], t, red, st);
     if constexpr (REC) {
         // scatter over the wavefront's own chunks (it reads only its own rows,
         // so a wavefront-level order suffices), point-major like the gather;
@@ -549,12 +555,12 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         wave_sync();
         const int lane = t & 63, c0w = t & ~63;
         const int cfb = c0w < w.nchunk ? c0w : 0;
-        int slot[CH];
-        T val[CH];
-        bool ok[CH];
+        int slot[C];
+        T val[C];
+        bool ok[C];
 #pragma unroll
-        for (int m = 0; m < CH; ++m) {
-            const int c = c0w + 4 * m + (lane >> 4), k = lane & (CH - 1);
+        for (int m = 0; m < C; ++m) {
+            const int c = c0w + CPS * m + lane / C, k = lane % C;
             const bool inc = c < w.nchunk;
             const int cc = inc ? c : cfb;
             const ChunkAddr a = s_ca[cc];
@@ -563,7 +569,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             val[m] = s_pt[cc * PS + k];
         }
 #pragma unroll
-        for (int m = 0; m < CH; ++m)
+        for (int m = 0; m < C; ++m)
             if (ok[m]) ub[slot[m]] = val[m];
     } else {
         __syncthreads();
@@ -581,7 +587,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 // 2D workgroups of NT/2 lanes address their points through the records
 // Workgroups of at most NT/2 lanes: at least three waves per SIMD, so at most
 // 168 VGPRs per lane
-template <typename T, int DIM, int NT, bool DOFF>
+template <typename T, int DIM, int NT, bool DOFF, int C = CH>
 __global__ void __launch_bounds__(NT, NT <= twmg::NT / 2 ? 3 : 2) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks,
                                                     const ChunkAddr *__restrict__ addrs,
@@ -591,8 +597,8 @@ __global__ void __launch_bounds__(NT, NT <= twmg::NT / 2 ? 3 : 2) k_block_sweep(
 {
     constexpr bool REC = DIM == 2 && NT <= twmg::NT / 2;
     const long long boff = (long long)blockIdx.y * d.bs;
-    sweep_wg<T, DIM, NT, DOFF, REC>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
-                                    rings);
+    sweep_wg<T, DIM, NT, DOFF, REC, C>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
+                                       rings);
 }
 
 template <typename T, int DIM, bool DOFF>
@@ -622,18 +628,28 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
     if (tab.nwg > tab.nwg_big) {
         const dim3 grid(tab.nwg - tab.nwg_big, batch);
         const WGDesc *wsm = tab.wgs + tab.nwg_big;
-        if (tab.nts == NT / 2) {
+        if (tab.nts == NT / 2 && tab.cap == CH) {
             hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, ss, d, c, u, f,
                                tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
         } else {
             if constexpr (DIM == 2) {
-                // narrow workgroups (2D levels bound by a workgroup's latency)
-                if (tab.nts == 64)
+                // narrow workgroups (2D levels bound by a workgroup's latency),
+                // with chunks of up to 16 or of up to 8 points
+                if (tab.nts == 64 && tab.cap == CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, ss, d, c, u, f,
                                        tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
-                else if (tab.nts == 128)
+                else if (tab.nts == 128 && tab.cap == CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF>), grid, dim3(128), 0, ss, d, c, u, f,
                                        tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 64 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF, SHORT_CH>), grid, dim3(64), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 128 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF, SHORT_CH>), grid, dim3(128), 0, ss, d, c, u,
+                                       f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == NT / 2 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF, SHORT_CH>), grid, dim3(NT / 2), 0, ss, d, c,
+                                       u, f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
                 else
                     return hipErrorInvalidValue;
             } else {

@@ -1228,7 +1228,9 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             const bool tail_size = L.d.nn * 2 * (long long)sizeof(double) <= TAIL_BYTES;
             int nmax = 0;
             for (int a = 0; a < dim; ++a) nmax = std::max(nmax, L.d.n[a]);
-            const int maxlen = !tail_size ? CH : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
+            const bool short_main = dim == 2 && !tail_size && nmax <= SHORT_CH_MAXN && !std::getenv("TWMG_LONG_CHUNKS");
+            const int maxlen =
+                !tail_size ? (short_main ? SHORT_CH : CH) : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
             std::vector<HostBlock> blocks;
             rc = build_blocks(L.g, h->slot_motif[s], blocks, maxlen);
             if (rc) return rc;
@@ -1267,6 +1269,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 T.nwg = (int)t.wgs.size();
                 T.nwg_big = t.nbig;
                 T.nts = t.nts;
+                T.cap = (dim == 2 && maxlen <= SHORT_CH) ? SHORT_CH : CH;
                 T.nchunk = (int)t.chunks.size();
                 T.nblock = (int)t.blocks.size();
                 for (const Block &bk : t.blocks)

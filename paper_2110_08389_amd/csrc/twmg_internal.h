@@ -15,6 +15,10 @@ constexpr int CH = 16;
 // spare entries on each side of a device coefficient block (a multiple of 2,
 // at least the CH + 2 entries of a chunk's coefficient window)
 constexpr int COEF_PAD = CH + 2;
+// chunk capacity on the 2D levels whose sweeps are bound by one workgroup's
+// latency (the lane's serial chains and its gather batches are half as long)
+constexpr int SHORT_CH = 8;
+constexpr int SHORT_CH_MAXN = 512; // levels with at most this many cells per axis
 
 // Direction codes: d = 2*axis + (positive ? 1 : 0); the reverse is d ^ 1.
 __host__ __device__ inline int dir_axis(int d) { return d >> 1; }
@@ -177,6 +181,7 @@ struct SweepTable {
     int nwg = 0, nchunk = 0, nblock = 0;
     int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others nts
     int nts = NT / 2; // lanes of the small workgroups: 64, 128 or NT/2 (2D only below NT/2)
+    int cap = CH;     // longest chunk: CH, or SHORT_CH (2D levels bound by a workgroup's latency)
     bool rings = false;
 };
 
