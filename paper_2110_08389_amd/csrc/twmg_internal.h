@@ -18,7 +18,7 @@ constexpr int COEF_PAD = CH + 2;
 // chunk capacity on the 2D levels whose sweeps are bound by one workgroup's
 // latency (the lane's serial chains and its gather batches are half as long)
 constexpr int SHORT_CH = 8;
-constexpr int SHORT_CH_MAXN = 512; // levels with at most this many cells per axis
+constexpr int SHORT_CH_MAXN = 1024; // levels with at most this many cells per axis
 
 // Direction codes: d = 2*axis + (positive ? 1 : 0); the reverse is d ^ 1.
 __host__ __device__ inline int dir_axis(int d) { return d >> 1; }
