@@ -386,7 +386,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
                                          const ChunkAddr *__restrict__ addrs, const T *__restrict__ cross,
                                          const Block *__restrict__ blocks, const WGDesc w,
-                                         const NodeFac<T> *__restrict__ fac, int rings, const SweepSync &sy)
+                                         const NodeFac<T> *__restrict__ fac, int rings)
 {
     static_assert(REC || C == CH, "short chunks only on the records path");
     static_assert(64 % C == 0 && C <= CH, "chunk capacity");
@@ -403,34 +403,6 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
     const int t = threadIdx.x;
     const bool act = t < w.nchunk;
-    // a workgroup of the colour relaxed second that runs during the first
-    // colour's half-sweep waits until the workgroups holding its neighbour
-    // blocks are done (bounded: on time-out its points get NaN, which the
-    // solve reports as divergence)
-    bool poison = false;
-    if (sy.wait) {
-        __shared__ int s_late;
-        if (t == 0) s_late = 0;
-        __syncthreads();
-        if (t < WAIT_MAX) {
-            const int slot = sy.wait[blockIdx.x * WAIT_MAX + t];
-            if (slot >= 0) {
-                const unsigned *fp = sy.flags + (size_t)blockIdx.y * sy.nslot + slot;
-                int it = 0;
-                while (__hip_atomic_load(fp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != sy.epoch) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (++it > (1 << 18)) {
-                        s_late = 1;
-                        break;
-                    }
-                }
-            }
-            // the neighbours' results become visible to this workgroup
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-        poison = s_late != 0;
-    }
     Chunk chl; // this lane's chunk
     if (act) {
         chl = chunks[w.chunk0 + t];
@@ -549,7 +521,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
                 const int cc = c < w.nchunk ? c : 0;
                 const Chunk ch = s_ch[cc];
                 const bool valid = c < w.nchunk && k < ch.len;
-                rv[m] = poison ? T(__builtin_nan("")) : point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
+                rv[m] = point_rhs_across<T, DIM>(d, cf, ub, fb, ch, valid ? k : 0);
                 dst[m] = valid ? c * PS + k : NT * PS;
             }
 #pragma unroll
@@ -609,16 +581,6 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             if (k < s_ch[c].len) ub[point_index(d, s_ch[c], k)] = s_pt[c * PS + k];
         }
     }
-    // the first colour's workgroups that hold neighbours of a waiting block
-    // publish their completion
-    if (sy.sig && sy.sig[blockIdx.x] >= 0) {
-        // each wave's stores reach the device-wide level before the flag is set
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (t == 0)
-            __hip_atomic_store(sy.flags + (size_t)blockIdx.y * sy.nslot + sy.sig[blockIdx.x], sy.epoch,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 // DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients);
@@ -631,58 +593,12 @@ __global__ void __launch_bounds__(NT, NT <= twmg::NT / 2 ? 3 : 2) k_block_sweep(
                                                     const ChunkAddr *__restrict__ addrs,
                                                     const T *__restrict__ cross, const Block *__restrict__ blocks,
                                                     const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
-                                                    int rings, SweepSync sy)
+                                                    int rings)
 {
     constexpr bool REC = DIM == 2 && NT <= twmg::NT / 2;
     const long long boff = (long long)blockIdx.y * d.bs;
     sweep_wg<T, DIM, NT, DOFF, REC, C>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
-                                       rings, sy);
-}
-
-// the NT-lane workgroups of a table (blocks of more than NT/2 chunks)
-template <typename T, int DIM, bool DOFF>
-static void launch_big(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
-                       const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s, const SweepSync &sy)
-{
-    hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
-                       tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, tab.rings ? 1 : 0, sy);
-}
-
-// the small workgroups of a table: NT/2 lanes, or narrower on 2D levels bound
-// by a workgroup's latency, with chunks of up to CH or up to SHORT_CH points
-template <typename T, int DIM, bool DOFF>
-static hipError_t launch_small(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
-                               const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s, const SweepSync &sy)
-{
-    const int rings = tab.rings ? 1 : 0;
-    const dim3 grid(tab.nwg - tab.nwg_big, batch);
-    const WGDesc *wsm = tab.wgs + tab.nwg_big;
-    if (tab.nts == NT / 2 && tab.cap == CH) {
-        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, s, d, c, u, f, tab.chunks,
-                           tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        return hipSuccess;
-    }
-    if constexpr (DIM == 2) {
-        if (tab.nts == 64 && tab.cap == CH)
-            hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, s, d, c, u, f, tab.chunks,
-                               tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        else if (tab.nts == 128 && tab.cap == CH)
-            hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF>), grid, dim3(128), 0, s, d, c, u, f, tab.chunks,
-                               tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        else if (tab.nts == 64 && tab.cap == SHORT_CH)
-            hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF, SHORT_CH>), grid, dim3(64), 0, s, d, c, u, f,
-                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        else if (tab.nts == 128 && tab.cap == SHORT_CH)
-            hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF, SHORT_CH>), grid, dim3(128), 0, s, d, c, u, f,
-                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        else if (tab.nts == NT / 2 && tab.cap == SHORT_CH)
-            hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF, SHORT_CH>), grid, dim3(NT / 2), 0, s, d, c, u, f,
-                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings, sy);
-        else
-            return hipErrorInvalidValue;
-        return hipSuccess;
-    }
-    return hipErrorInvalidValue;
+                                       rings);
 }
 
 template <typename T, int DIM, bool DOFF>
@@ -690,25 +606,58 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
                                    const NodeFac<T> *fac, const T *cross, int batch, hipStream_t s,
                                    const SideStream &side)
 {
-    // workgroups holding a block of more than NT/2 chunks run with NT lanes,
-    // the rest with NT/2 lanes or fewer, so that several workgroups share a
-    // CU and hide each other's memory waits.  The NT-lane launch goes first,
-    // on the caller's stream, so that its few large workgroups are placed
-    // before the others fill the CUs; with a side stream the other launch
-    // overlaps it.
+    const int rings = tab.rings ? 1 : 0;
+    // workgroups holding a block of more than NT/2 chunks come first and run
+    // with NT lanes; the rest run with NT/2 lanes (a third of the LDS), so that
+    // several workgroups share a CU and hide each other's memory waits.  With
+    // a side stream the NT-lane launch overlaps the other one.
+    // the NT-lane launch goes first, on the caller's stream, so that its few
+    // large workgroups are placed before the NT/2-lane ones fill the CUs
     const bool both = tab.nwg_big > 0 && tab.nwg > tab.nwg_big;
     const bool fork = both && side.aux != nullptr;
-    hipStream_t ss = s;
+    static const bool big_aux = std::getenv("TWMG_BIG_AUX") != nullptr;
+    hipStream_t ss = s, sb = s;
     if (fork) {
         hipError_t e = hipEventRecord(side.fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(side.aux, side.fork, 0);
         if (e != hipSuccess) return e;
-        ss = side.aux;
+        if (big_aux) sb = side.aux;
+        else ss = side.aux;
     }
-    if (tab.nwg_big > 0) launch_big<T, DIM, DOFF>(d, c, u, f, tab, fac, cross, batch, s, SweepSync());
+    if (tab.nwg_big > 0)
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, sb, d, c, u, f,
+                           tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big) {
-        const hipError_t e = launch_small<T, DIM, DOFF>(d, c, u, f, tab, fac, cross, batch, ss, SweepSync());
-        if (e != hipSuccess) return e;
+        const dim3 grid(tab.nwg - tab.nwg_big, batch);
+        const WGDesc *wsm = tab.wgs + tab.nwg_big;
+        if (tab.nts == NT / 2 && tab.cap == CH) {
+            hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, ss, d, c, u, f,
+                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+        } else {
+            if constexpr (DIM == 2) {
+                // narrow workgroups (2D levels bound by a workgroup's latency),
+                // with chunks of up to 16 or of up to 8 points
+                if (tab.nts == 64 && tab.cap == CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 128 && tab.cap == CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF>), grid, dim3(128), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 64 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF, SHORT_CH>), grid, dim3(64), 0, ss, d, c, u, f,
+                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == 128 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF, SHORT_CH>), grid, dim3(128), 0, ss, d, c, u,
+                                       f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else if (tab.nts == NT / 2 && tab.cap == SHORT_CH)
+                    hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF, SHORT_CH>), grid, dim3(NT / 2), 0, ss, d, c,
+                                       u, f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                else
+                    return hipErrorInvalidValue;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        }
     }
     if (fork) {
         hipError_t e = hipEventRecord(side.join, side.aux);
@@ -719,8 +668,12 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
 }
 
 template <typename T>
-static void table_arrays(const SweepTable &tab, int adj, const NodeFac<T> *&fac, const T *&cross)
+hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
+                              int batch, hipStream_t s, const SideStream &side)
 {
+    if (tab.nwg == 0) return hipSuccess;
+    const NodeFac<T> *fac;
+    const T *cross;
     if constexpr (sizeof(T) == 8) {
         fac = tab.fac64[adj];
         cross = tab.cross64[adj];
@@ -728,16 +681,6 @@ static void table_arrays(const SweepTable &tab, int adj, const NodeFac<T> *&fac,
         fac = tab.fac32[adj];
         cross = tab.cross32[adj];
     }
-}
-
-template <typename T>
-hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
-                              int batch, hipStream_t s, const SideStream &side)
-{
-    if (tab.nwg == 0) return hipSuccess;
-    const NodeFac<T> *fac;
-    const T *cross;
-    table_arrays<T>(tab, adj, fac, cross);
     const bool doff = sizeof(T) == 8 && adj == 0;
     hipError_t e;
     if (d.dim == 2) {
@@ -747,46 +690,6 @@ hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f,
         if (doff) e = launch_sweep_dim<T, 3, true>(d, c, u, f, tab, fac, cross, batch, s, side);
         else e = launch_sweep_dim<T, 3, false>(d, c, u, f, tab, fac, cross, batch, s, side);
     }
-    if (e != hipSuccess) return e;
-    return hipGetLastError();
-}
-
-// Both colours of a 2D forward relaxation.  The second colour's NT-lane
-// workgroups go to the side stream together with the first colour's launch,
-// each gated by the flags of the first colour's workgroups that hold its
-// neighbour blocks, so that they run during the first half-sweep instead of
-// lengthening the second; the caller's stream waits for them after the
-// second colour's small workgroups.
-template <typename T>
-hipError_t launch_block_sweep_pair(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &first,
-                                   const SweepTable &second, int batch, hipStream_t s, const SideStream &side,
-                                   unsigned *flags, unsigned epoch)
-{
-    if (d.dim != 2 || !second.paired || side.aux == nullptr || first.nwg_big != 0 || second.nwg_big == 0 ||
-        second.nwg == second.nwg_big)
-        return hipErrorInvalidValue;
-    constexpr bool DOFF = sizeof(T) == 8;
-    const NodeFac<T> *fac1, *fac2;
-    const T *cross1, *cross2;
-    table_arrays<T>(first, 0, fac1, cross1);
-    table_arrays<T>(second, 0, fac2, cross2);
-    SweepSync sig, wait;
-    sig.sig = first.sig;
-    wait.wait = second.wait;
-    sig.flags = wait.flags = flags + second.flag_off;
-    sig.epoch = wait.epoch = epoch;
-    sig.nslot = wait.nslot = second.nslot;
-    // the first colour is queued before the waiting workgroups: should the
-    // two streams share a hardware queue, the waiting launch then simply
-    // runs after it
-    hipError_t e = hipEventRecord(side.fork, s);
-    if (e == hipSuccess) e = launch_small<T, 2, DOFF>(d, c, u, f, first, fac1, cross1, batch, s, sig);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side.aux, side.fork, 0);
-    if (e != hipSuccess) return e;
-    launch_big<T, 2, DOFF>(d, c, u, f, second, fac2, cross2, batch, side.aux, wait);
-    e = hipEventRecord(side.join, side.aux);
-    if (e == hipSuccess) e = launch_small<T, 2, DOFF>(d, c, u, f, second, fac2, cross2, batch, s, SweepSync());
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, side.join, 0);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1738,9 +1641,6 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
 #define TWMG_INST(T)                                                                                                  \
     template hipError_t launch_block_sweep<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, int, \
                                               int, hipStream_t, const SideStream &);                                  \
-    template hipError_t launch_block_sweep_pair<T>(const Dims &, const Coef<T> &, T *, const T *, const SweepTable &, \
-                                                   const SweepTable &, int, hipStream_t, const SideStream &, unsigned *, \
-                                                   unsigned);                                                             \
     template hipError_t launch_checker<T>(const Dims &, const Coef<T> &, T *, const T *, int, int, hipStream_t);     \
     template hipError_t launch_residual<T>(const Dims &, const Dims &, const Coef<T> &, const T *, const T *, T *,  \
                                            int, hipStream_t);                                                         \

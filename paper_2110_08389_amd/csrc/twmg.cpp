@@ -6,7 +6,6 @@
 
 #include <algorithm>
 #include <chrono>
-#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -786,8 +785,6 @@ struct mg_handle {
     mg_options opt;
     hipStream_t stream = nullptr;
     SideStream side;          // overlaps big-block launches with the rest of a half-sweep
-    unsigned *flags = nullptr; // completion flags of paired relaxations (SweepTable::paired)
-    unsigned epoch = 0;        // value the flags take in the latest paired relaxation
     int nlev = 0;
     Level lev[MAXLEV];
     int slot_motif[2] = {-1, -1};
@@ -1062,8 +1059,6 @@ void free_tail(mg_handle *h)
         }
     h->tail_lv = -1;
 }
-
-int build_pairs(mg_handle *h);
 
 int build_tail(mg_handle *h)
 {
@@ -1347,80 +1342,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             HIPCHK(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
         }
     }
-    if ((rc = build_pairs(h))) return rc;
     h->ws_bytes = workspace_layout(h, false);
-    return MG_OK;
-}
-
-// Pairing of the two half-sweeps of a 2D forward relaxation (launch_block_sweep_pair):
-// for every NT-lane workgroup of the colour relaxed second, the workgroups of
-// the first colour that hold a stencil neighbour of one of its points (the
-// only points its sweep reads besides its own, and the only ones that read
-// its points).  A level is paired when the first colour has no NT-lane
-// workgroups and each NT-lane workgroup of the second has at most WAIT_MAX
-// such neighbours.
-int build_pairs(mg_handle *h)
-{
-    if (h->pool.host_only || !h->side.aux || h->grid.dim != 2 || std::getenv("TWMG_NO_PAIR")) return MG_OK;
-    const int B = h->grid.batch;
-    long long total = 0;
-    std::vector<int> owner;
-    for (int l = 0; l + 1 < h->nlev; ++l) {
-        Level &L = h->lev[l];
-        const Grid3 &g = L.g;
-        const long long np0 = g.n[0] + 1;
-        for (int s = 0; s < 2; ++s) {
-            if (h->slot_motif[s] < 0) continue;
-            const HostTable &t1 = L.htab[s][0], &t2 = L.htab[s][1];
-            if (t1.nbig != 0 || t1.wgs.empty() || t2.nbig == 0 || (int)t2.wgs.size() == t2.nbig) continue;
-            owner.assign((size_t)np0 * (g.n[1] + 1), -1);
-            auto each_point = [&](const HostTable &t, const WGDesc &w, auto fn) {
-                for (int q = w.chunk0; q < w.chunk0 + w.nchunk; ++q) {
-                    const Chunk &c = t.chunks[q];
-                    const int ax = c.axdir >> 1, sg = (c.axdir & 1) ? 1 : -1;
-                    int p[2] = {c.c0[0], c.c0[1]};
-                    for (int k = 0; k < c.len; ++k, p[ax] += sg) fn(p[0], p[1]);
-                }
-            };
-            for (size_t wi = 0; wi < t1.wgs.size(); ++wi)
-                each_point(t1, t1.wgs[wi], [&](int i, int j) { owner[i + j * np0] = (int)wi; });
-            std::vector<int> sig(t1.wgs.size(), -1), wait((size_t)t2.nbig * WAIT_MAX, -1);
-            int nslot = 0;
-            bool ok = true;
-            for (int wi = 0; wi < t2.nbig && ok; ++wi) {
-                std::vector<int> dep;
-                each_point(t2, t2.wgs[wi], [&](int i, int j) {
-                    const int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
-                    for (const auto &q : nb) {
-                        if (!g.interior(q[0], q[1], 0)) continue;
-                        const int o = owner[q[0] + q[1] * np0];
-                        if (o >= 0 && std::find(dep.begin(), dep.end(), o) == dep.end()) dep.push_back(o);
-                    }
-                });
-                if ((int)dep.size() > WAIT_MAX) ok = false;
-                for (size_t k = 0; k < dep.size() && ok; ++k) {
-                    if (sig[dep[k]] < 0) sig[dep[k]] = nslot++;
-                    wait[(size_t)wi * WAIT_MAX + k] = sig[dep[k]];
-                }
-            }
-            if (!ok) continue;
-            int err = 0;
-            SweepTable &T1 = L.tab[s][0], &T2 = L.tab[s][1];
-            T1.sig = h->pool.upload(sig, err);
-            T2.wait = h->pool.upload(wait, err);
-            if (err) return err;
-            T2.flag_off = (int)total;
-            T2.nslot = nslot;
-            T2.paired = true;
-            total += (long long)B * nslot;
-        }
-    }
-    if (total > 0) {
-        if (total > INT_MAX) return MG_EUNSUPPORTED;
-        int err = 0;
-        h->flags = h->pool.upload(std::vector<unsigned>((size_t)total, 0u), err);
-        if (err) return err;
-    }
     return MG_OK;
 }
 
@@ -1454,12 +1376,6 @@ template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
     const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
     for (int k = 0; k < ns; ++k) {
         const int s = adj ? ns - 1 - k : k;
-        if (!adj && L.tab[s][1].paired) {
-            if (++h->epoch == 0) h->epoch = 1;
-            HIPCHK(launch_block_sweep_pair<T>(L.d, c, u, f, L.tab[s][0], L.tab[s][1], B, h->stream, h->side, h->flags,
-                                              h->epoch));
-            continue;
-        }
         for (int q = 0; q < 2; ++q) {
             const int colour = adj ? 1 - q : q;
             HIPCHK(launch_block_sweep<T>(L.d, c, u, f, L.tab[s][colour], adj, B, h->stream, h->side));

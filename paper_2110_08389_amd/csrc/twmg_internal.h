@@ -182,16 +182,6 @@ struct SweepTable {
     int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others nts
     int nts = NT / 2; // lanes of the small workgroups: 64, 128 or NT/2 (2D only below NT/2)
     int cap = CH;     // longest chunk: CH, or SHORT_CH (2D levels bound by a workgroup's latency)
-    // Overlap of this colour's NT-lane workgroups with the other colour's
-    // half-sweep (see SweepSync): sig, per small workgroup of the colour
-    // relaxed first, the flag slot it sets when done (-1: none); wait, per
-    // NT-lane workgroup of the colour relaxed second, WAIT_MAX slots it waits
-    // for (-1: unused).  flag_off: this level's first slot in the handle's
-    // flag array; nslot: its slots per problem.
-    int *sig = nullptr;
-    int *wait = nullptr;
-    int flag_off = 0, nslot = 0;
-    bool paired = false; // the colour relaxed second waits through flags (set on that colour's table)
     bool rings = false;
 };
 
@@ -243,19 +233,6 @@ template <typename T> struct TailPlan {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
-// Flags that let the NT-lane workgroups of the colour relaxed second (a
-// block of more than NT/2 chunks) run during the first colour's half-sweep:
-// each waits until the first colour's workgroups holding its neighbour blocks
-// have set their flags to this half-sweep's epoch.
-constexpr int WAIT_MAX = 8;
-struct SweepSync {
-    const int *sig = nullptr;  // small launch: flag slot per workgroup (-1: none)
-    const int *wait = nullptr; // NT-lane launch: WAIT_MAX flag slots per workgroup (-1: unused)
-    unsigned *flags = nullptr; // nslot flags per problem of the batch
-    unsigned epoch = 0;
-    int nslot = 0;
-};
-
 // Side stream for the NT-lane workgroups of a half-sweep: blocks of one colour
 // are independent, so the big-block launch runs beside the NT/2-lane one
 // (fork and join through the two events).  aux == nullptr: one stream.
@@ -267,13 +244,6 @@ struct SideStream {
 template <typename T>
 hipError_t launch_block_sweep(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab, int adj,
                               int batch, hipStream_t s, const SideStream &side = SideStream());
-// Both half-sweeps of one relaxation, first colour then second, where the
-// second colour's NT-lane workgroups run on the side stream during the first
-// half-sweep, gated by flags (second.paired; forward operator order only).
-template <typename T>
-hipError_t launch_block_sweep_pair(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &first,
-                                   const SweepTable &second, int batch, hipStream_t s, const SideStream &side,
-                                   unsigned *flags, unsigned epoch);
 template <typename T>
 hipError_t launch_checker(const Dims &d, const Coef<T> &c, T *u, const T *f, int colour, int batch, hipStream_t s);
 template <typename T>

@@ -4,12 +4,9 @@ tweed V(2,2) cycles in FP64, with the solver set up exactly as the benchmark
 sets it up.  The oracle finishes one relaxation of this grid in about 2 s and
 one V-cycle in about 10 s, so the comparison is element by element over the
 whole array, at the tolerances of the smaller parity cases (1e-12 relative in
-the max-norm).
-
-At this size the largest tweed blocks of the second colour exceed half a
-workgroup and run in their own launch; on the forward relaxation that launch
-runs during the first colour's half-sweep, gated by completion flags.  The
-same relaxation without that overlap must give the same bits.
+the max-norm).  At this size the finest level's black colour holds a block of
+512 chunks (the centre cross), which runs as a 512-lane workgroup in a launch
+of its own beside the other black workgroups.
 """
 import numpy as np
 import pytest
@@ -84,17 +81,3 @@ def test_fullsize_vcycle(problem):
     uo = H.cycle(u0, f)
     assert rel_inf(N(ug), uo) < 1e-12, rel_inf(N(ug), uo)
     del s
-
-
-def test_fullsize_overlap_gives_same_bits(problem, monkeypatch):
-    _, u0, f = problem
-    out = []
-    for off in (False, True):
-        if off:
-            monkeypatch.setenv("TWMG_NO_PAIR", "1")
-        s = solver()
-        ug = T(u0)
-        s.smooth(ug, T(f), nu=2)
-        out.append(N(ug))
-        del s
-    assert np.array_equal(out[0], out[1])
