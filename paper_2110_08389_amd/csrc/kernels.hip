@@ -615,17 +615,15 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
     // large workgroups are placed before the NT/2-lane ones fill the CUs
     const bool both = tab.nwg_big > 0 && tab.nwg > tab.nwg_big;
     const bool fork = both && side.aux != nullptr;
-    static const bool big_aux = std::getenv("TWMG_BIG_AUX") != nullptr;
-    hipStream_t ss = s, sb = s;
+    hipStream_t ss = s;
     if (fork) {
         hipError_t e = hipEventRecord(side.fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(side.aux, side.fork, 0);
         if (e != hipSuccess) return e;
-        if (big_aux) sb = side.aux;
-        else ss = side.aux;
+        ss = side.aux;
     }
     if (tab.nwg_big > 0)
-        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, sb, d, c, u, f,
+        hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
                            tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big) {
         const dim3 grid(tab.nwg - tab.nwg_big, batch);
