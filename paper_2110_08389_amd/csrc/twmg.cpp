@@ -1231,12 +1231,27 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             const bool short_main = dim == 2 && !tail_size && nmax <= SHORT_CH_MAXN && !std::getenv("TWMG_LONG_CHUNKS");
             const int maxlen =
                 !tail_size ? (short_main ? SHORT_CH : CH) : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
-            std::vector<HostBlock> blocks;
+            std::vector<HostBlock> blocks, short_blocks;
             rc = build_blocks(L.g, h->slot_motif[s], blocks, maxlen);
             if (rc) return rc;
+            // on the larger 2D levels, a colour whose blocks all still fit
+            // NT/2 lanes with chunks of SHORT_CH points takes those (shorter
+            // chains per lane; a colour with a larger block keeps CH)
+            bool short_colour[2] = {maxlen <= SHORT_CH && dim == 2, maxlen <= SHORT_CH && dim == 2};
+            if (dim == 2 && !tail_size && maxlen == CH && !std::getenv("TWMG_LONG_CHUNKS")) {
+                rc = build_blocks(L.g, h->slot_motif[s], short_blocks, SHORT_CH);
+                if (rc == MG_EUNSUPPORTED) short_blocks.clear(); // a block beyond NT chunks
+                else if (rc) return rc;
+                for (int colour = 0; colour < 2; ++colour) {
+                    bool fits = !short_blocks.empty();
+                    for (const HostBlock &hb : short_blocks)
+                        if (hb.colour == colour && (int)hb.ch.size() > NT / 2) fits = false;
+                    short_colour[colour] = fits;
+                }
+            }
             for (int colour = 0; colour < 2; ++colour) {
                 std::vector<const HostBlock *> sel;
-                for (const HostBlock &hb : blocks)
+                for (const HostBlock &hb : short_colour[colour] && maxlen == CH ? short_blocks : blocks)
                     if (hb.colour == colour) sel.push_back(&hb);
                 HostTable &t = L.htab[s][colour];
                 // narrow workgroups for 2D levels too large for the
@@ -1269,7 +1284,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 T.nwg = (int)t.wgs.size();
                 T.nwg_big = t.nbig;
                 T.nts = t.nts;
-                T.cap = (dim == 2 && maxlen <= SHORT_CH) ? SHORT_CH : CH;
+                T.cap = short_colour[colour] ? SHORT_CH : CH;
                 T.nchunk = (int)t.chunks.size();
                 T.nblock = (int)t.blocks.size();
                 for (const Block &bk : t.blocks)
@@ -1627,9 +1642,18 @@ int mg_solve(mg_handle *h, double *u, const double *f, const double *bc, double 
     Level &L = h->lev[0];
     const int B = h->grid.batch;
     const bool zero = !(h->opt.flags & MG_INITIAL_GUESS);
-    if (bc || zero) HIPCHK(launch_set_boundary(row_dims(L.d), u, bc, zero ? 1 : 0, B, h->stream));
-    if (!split(L)) return solve_impl(h, u, f, tol, stats, 0);
-    HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+    if (!split(L)) {
+        if (bc || zero) HIPCHK(launch_set_boundary(row_dims(L.d), u, bc, zero ? 1 : 0, B, h->stream));
+        return solve_impl(h, u, f, tol, stats, 0);
+    }
+    if (zero) {
+        // the start is the boundary data and a zero interior: written straight
+        // into the level's layout (the caller's u gets every node on return)
+        HIPCHK(launch_set_boundary(L.d, L.u, bc ? bc : u, 1, B, h->stream));
+    } else {
+        if (bc) HIPCHK(launch_set_boundary(row_dims(L.d), u, bc, 0, B, h->stream));
+        HIPCHK(launch_convert<double>(L.d, u, L.u, 1, B, h->stream));
+    }
     HIPCHK(launch_convert<double>(L.d, f, L.f, 1, B, h->stream));
     rc = solve_impl(h, L.u, L.f, tol, stats, 0);
     HIPCHK(launch_convert<double>(L.d, L.u, u, 0, B, h->stream));
