@@ -144,7 +144,9 @@ __device__ __forceinline__ float lane_value(float v, int lane)
 // the composition of the maps of lanes 0..t (later maps applied last).  Rows
 // of 16 lanes by DPP shifts, the 4 rows of a wave through their totals (lane
 // reads), the waves of the workgroup through per-wave totals sa/sb in LDS.
-template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa, T *sb)
+// ONEWAVE: only wavefront 0 takes part (all other lanes of the workgroup are
+// elsewhere), so the wavefront's own scan is the whole scan
+template <typename T, bool ONEWAVE = false> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa, T *sb)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
     {
@@ -176,6 +178,7 @@ template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa
         B = A * pB + B;
         A = A * pA;
     }
+    if constexpr (ONEWAVE) return;
     if (lane == 63) {
         sa[wv] = A;
         sb[wv] = B;
@@ -192,7 +195,7 @@ template <typename T> __device__ __forceinline__ void scan_fwd(T &A, T &B, T *sa
 }
 
 // the same over lanes in decreasing order (composition of the maps of lanes t..NT-1)
-template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa, T *sb)
+template <typename T, bool ONEWAVE = false> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa, T *sb)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6, row = lane >> 4;
     {
@@ -224,6 +227,7 @@ template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa
         B = A * pB + B;
         A = A * pA;
     }
+    if constexpr (ONEWAVE) return;
     if (lane == 0) {
         sa[wv] = A;
         sb[wv] = B;
@@ -239,6 +243,21 @@ template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa
     __syncthreads();
 }
 
+// Workgroup barrier, or with ONEWAVE (only wavefront 0 runs this code) the
+// ordering of one wavefront's LDS accesses: a wavefront's LDS instructions
+// execute in issue order, so only the compiler has to be kept from moving
+// them across this point.
+template <bool ONEWAVE> __device__ __forceinline__ void wg_sync()
+{
+    if constexpr (ONEWAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Block-relaxation half-sweep: one lane per chunk.  The workgroup's points are
 // gathered point-major (consecutive lanes read consecutive points of a chunk,
 // so rows are read in whole cache lines) into an LDS staging buffer; each lane
@@ -252,7 +271,7 @@ template <typename T> __device__ __forceinline__ void scan_bwd(T &A, T &B, T *sa
 // s_nf (4 NT entries of LDS that are free during this phase), each node
 // publishes its factors there and the branch-point and ring-border lanes read
 // them from LDS; without it they read fac.
-template <typename T>
+template <typename T, bool ONEWAVE = false>
 __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint8_t nfl, int ext, const NodeFac<T> &nf,
                                                  const Block &bk, const NodeFac<T> *__restrict__ fac, int rings,
                                                  T *s_rs, T *s_rn, T *s_dl, T *s_x, T *s_a, T *s_b, T *s_nf)
@@ -280,10 +299,10 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
         A = (nfl & NF_HEAD) ? T(0) : nf.alpha;
         B = rhs * nf.inv;
     }
-    scan_fwd<T>(A, B, s_a, s_b);
+    scan_fwd<T, ONEWAVE>(A, B, s_a, s_b);
     const T dl = B;
     s_dl[t] = dl;
-    __syncthreads();
+    wg_sync<ONEWAVE>();
     // branch points of the spiders
     if (t < w.nblock && bk.type == BT_SPIDER) {
         const int first = bk.first, J = first + bk.count - 1, m = bk.m;
@@ -298,7 +317,7 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
         if (J > first) num -= fj.gam * s_dl[J - 1];
         s_x[J] = num * fj.inv;
     }
-    __syncthreads();
+    wg_sync<ONEWAVE>();
     // back substitution along segments
     A = 0;
     B = 0;
@@ -311,19 +330,19 @@ __device__ __forceinline__ void reduced_solve_wg(const WGDesc &w, bool act, uint
             B = dl;
         }
     }
-    scan_bwd<T>(A, B, s_a, s_b);
+    scan_bwd<T, ONEWAVE>(A, B, s_a, s_b);
     T x = B;
     if (act && !(nfl & (NF_J | NF_B))) s_x[t] = x;
     if (rings) {
-        __syncthreads();
+        wg_sync<ONEWAVE>();
         if (t < w.nblock && bk.type == BT_RING) {
             const int s0 = bk.first, Bn = bk.first + bk.count - 1;
             const NodeFac<T> fb_ = node_fac(Bn);
             s_x[Bn] = (s_rs[Bn] + s_rn[Bn] - fb_.alpha * s_x[Bn - 1] - fb_.gam * s_x[s0]) * fb_.inv;
         }
-        __syncthreads();
+        wg_sync<ONEWAVE>();
         if (act && (nfl & NF_RING)) x -= s_x[ext] * nf.z;
-        __syncthreads();
+        wg_sync<ONEWAVE>();
         if (act && (nfl & NF_RING)) s_x[t] = x;
     }
 }
@@ -1142,8 +1161,10 @@ hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f
 // Block sweep of one workgroup descriptor with u, f, coefficients and tables
 // in LDS: each lane forms its chunk's right-hand sides directly (no staging),
 // phases 1-3 as in the main sweep, new values written in place.
-// C: the longest chunk of the level (the code runs over C positions per lane)
-template <typename T, int DIM, int C>
+// C: the longest chunk of the level (the code runs over C positions per lane).
+// ONEWAVE: the descriptor's chunks and blocks all sit in wavefront 0, which
+// runs this alone (the other wavefronts skip the operation).
+template <typename T, int DIM, int C, bool ONEWAVE = false>
 __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, T *ub, const T *fb,
                                               const Chunk *chunks, const Block *blocks, const WGDesc w,
                                               const NodeFac<T> *fac, int rings, T *s_rs, T *s_rn, T *s_dl, T *s_x,
@@ -1187,12 +1208,13 @@ __device__ __forceinline__ void sweep_wg_tail(const Dims &d, const Coef<T> &cf, 
         sweep_phase1<T, DIM, false, true, false, C>(
             d, cf, [&](int k) { return k == 0 ? R[0] - tb : R[k]; }, rL, ch, t, red, st);
     }
-    __syncthreads();
+    wg_sync<ONEWAVE>();
     Block bk;
     bk.type = BT_CHAIN;
     if (t < w.nblock) bk = blocks[w.block0 + t];
-    reduced_solve_wg<T>(w, act, nfl, ext, nf, bk, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b, (T *)nullptr);
-    __syncthreads();
+    reduced_solve_wg<T, ONEWAVE>(w, act, nfl, ext, nf, bk, fac, rings, s_rs, s_rn, s_dl, s_x, s_a, s_b,
+                                  (T *)nullptr);
+    wg_sync<ONEWAVE>();
     if (act) {
         if (DIM == 2) {
             const ChunkAddr a = row_chunk_addr(d, ch);
@@ -1243,14 +1265,31 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
             const Block *blocks = reinterpret_cast<const Block *>(s_mem + L.block_off[sl][c]);
             const WGDesc *wgs = reinterpret_cast<const WGDesc *>(s_mem + L.wg_off[sl][c]);
             const NodeFac<T> *fac = reinterpret_cast<const NodeFac<T> *>(s_mem + L.fac_off[sl][c]);
-            for (int w = 0; w < nw; ++w) {
-                if (L.short_chunks)
-                    sweep_wg_tail<T, DIM, TAIL_SHORT_CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c],
-                                                         s_rs, s_rn, s_dl, s_x, s_a, s_b);
-                else
-                    sweep_wg_tail<T, DIM, CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c], s_rs, s_rn,
-                                              s_dl, s_x, s_a, s_b);
-                __syncthreads();
+            if (L.onewave[sl][c]) {
+                // every descriptor fits wavefront 0: it alone runs the
+                // sweep, with no workgroup barrier until the operation's end
+                if (threadIdx.x < 64) {
+                    for (int w = 0; w < nw; ++w) {
+                        if (L.short_chunks)
+                            sweep_wg_tail<T, DIM, TAIL_SHORT_CH, true>(d, cf, us, fs, chunks, blocks, wgs[w], fac,
+                                                                       L.rings[sl][c], s_rs, s_rn, s_dl, s_x, s_a,
+                                                                       s_b);
+                        else
+                            sweep_wg_tail<T, DIM, CH, true>(d, cf, us, fs, chunks, blocks, wgs[w], fac,
+                                                            L.rings[sl][c], s_rs, s_rn, s_dl, s_x, s_a, s_b);
+                        wave_sync();
+                    }
+                }
+            } else {
+                for (int w = 0; w < nw; ++w) {
+                    if (L.short_chunks)
+                        sweep_wg_tail<T, DIM, TAIL_SHORT_CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac,
+                                                             L.rings[sl][c], s_rs, s_rn, s_dl, s_x, s_a, s_b);
+                    else
+                        sweep_wg_tail<T, DIM, CH>(d, cf, us, fs, chunks, blocks, wgs[w], fac, L.rings[sl][c], s_rs,
+                                                  s_rn, s_dl, s_x, s_a, s_b);
+                    __syncthreads();
+                }
             }
         } else if (op.kind == TO_CHECKER) {
             const int nx = d.n[0] - 1, ny = d.n[1] - 1, nz = DIM == 3 ? d.n[2] - 1 : 1;

@@ -1028,6 +1028,9 @@ size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char
                 t.nwg[sl][c] = (int)ht.wgs.size();
                 for (const Block &bk : ht.blocks)
                     if (bk.type == BT_RING) t.rings[sl][c] = 1;
+                t.onewave[sl][c] = std::getenv("TWMG_NO_ONEWAVE") ? 0 : 1;
+                for (const WGDesc &w : ht.wgs)
+                    if (w.nchunk > 64 || w.nblock > 64) t.onewave[sl][c] = 0;
             }
     }
     size_t off = align16(I.b.size());

@@ -217,6 +217,7 @@ struct TailLevel {
     int nwg[2][2];
     int rings[2][2];
     int short_chunks;  // every chunk of the level has at most TAIL_SHORT_CH points
+    int onewave[2][2]; // every descriptor of the table has at most 64 chunks and 64 blocks
 };
 
 template <typename T> struct TailPlan {
