@@ -1318,6 +1318,25 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
                 const int i = 1 + q % nx, j = 1 + (q / nx) % ny, l = DIM == 3 ? 1 + q / (nx * ny) : 0;
                 us[i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0)] += prolong_at<T, DIM>(cd, uc, i, j, l);
             }
+        } else if (op.kind == TO_MAP) {
+            // the level's sub-cycle in one step: each lane forms one unknown's
+            // new value from all old values and right-hand sides, then all write
+            const int nx = d.n[0] - 1, ny = d.n[1] - 1, nu = P.map_nu;
+            const int i = threadIdx.x;
+            T acc = 0;
+            long long slot = 0;
+            if (i < nu) {
+                for (int k = 0; k < nu; ++k) {
+                    const int ik = 1 + k % nx, jk = 1 + (k / nx) % ny, lk = DIM == 3 ? 1 + k / (nx * ny) : 0;
+                    const long long pk = ik + jk * d.st[1] + (DIM == 3 ? lk * d.st[2] : 0);
+                    acc += P.map[(long long)k * nu + i] * us[pk];
+                    acc += P.map[(long long)(nu + k) * nu + i] * fs[pk];
+                }
+                const int ii = 1 + i % nx, ji = 1 + (i / nx) % ny, li = DIM == 3 ? 1 + i / (nx * ny) : 0;
+                slot = ii + ji * d.st[1] + (DIM == 3 ? li * d.st[2] : 0);
+            }
+            __syncthreads();
+            if (i < nu) us[slot] = acc;
         } else { // TO_SOLVE
             coarse_solve_wg<T, DIM>(d, cf, us, fs, P.ainv, P.nunk, arr(P.rhs_off));
         }

@@ -804,6 +804,8 @@ struct mg_handle {
     TailPlan<double> tail64[2];
     TailPlan<float> tail32[2];
     int tail_key[4] = {-1, -1, -1, -1}; // checker, nu1, nu2, gamma the images were built for
+    int tail_map_lv = -1;  // level whose sub-cycle the coarse-level kernel applies as a map (-1: none)
+    void *tail_map[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // [FP64, FP32][forward, transposed]
 };
 
 namespace {
@@ -952,6 +954,10 @@ void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, std::vector<TailO
         ops.push_back(TailOp{TO_SOLVE, rel, 0, 0});
         return;
     }
+    if (lv == h->tail_map_lv) {
+        ops.push_back(TailOp{TO_MAP, rel, 0, 0});
+        return;
+    }
     auto relax = [&]() {
         if (h->checker) {
             for (int k = 0; k < 2; ++k) ops.push_back(TailOp{TO_CHECKER, rel, 0, (uint8_t)(adj ? 1 - k : k)});
@@ -1060,7 +1066,67 @@ void free_tail(mg_handle *h)
             if (p) (void)hipFree(p);
             p = nullptr;
         }
+    for (auto &row : h->tail_map)
+        for (void *&p : row) {
+            if (p) (void)hipFree(p);
+            p = nullptr;
+        }
     h->tail_lv = -1;
+    h->tail_map_lv = -1;
+}
+
+// The sub-cycle of level lm (zero boundary values, nu <= TAIL_MAP_MAX
+// interior unknowns) is linear in the level's u and f: it is computed once by
+// the coarse-level kernel itself, started at lm, on the 2 nu unit vectors as a
+// batch, and stored input-major for TailPlan::map.  lm's operations must be
+// the plain ones (tail_map_lv < 0) while this runs.
+template <typename T> int build_tail_map(mg_handle *h, int lm, int adj, void **out)
+{
+    const Level &L = h->lev[lm];
+    const Dims &d = L.d;
+    const int nx = d.n[0] - 1, ny = d.n[1] - 1, nz = d.dim == 3 ? d.n[2] - 1 : 1;
+    const int nu = nx * ny * nz, nb = 2 * nu;
+    const long long nn = d.nn;
+    auto node = [&](int k) {
+        return (long long)(1 + k % nx) + (long long)(1 + (k / nx) % ny) * d.st[1] +
+               (d.dim == 3 ? (long long)(1 + k / (nx * ny)) * d.st[2] : 0);
+    };
+    std::vector<unsigned char> img;
+    TailPlan<T> p;
+    tail_image<T>(h, lm, adj, img, p);
+    std::vector<T> hu((size_t)nb * nn, T(0)), hf((size_t)nb * nn, T(0));
+    for (int k = 0; k < nu; ++k) {
+        hu[(size_t)k * nn + node(k)] = T(1);
+        hf[(size_t)(nu + k) * nn + node(k)] = T(1);
+    }
+    void *dimg = nullptr, *du = nullptr, *df = nullptr;
+    int rc = MG_OK;
+    if (hipMalloc(&dimg, img.size()) != hipSuccess || hipMalloc(&du, hu.size() * sizeof(T)) != hipSuccess ||
+        hipMalloc(&df, hf.size() * sizeof(T)) != hipSuccess)
+        rc = MG_ENOMEM;
+    if (!rc && (hipMemcpy(dimg, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(du, hu.data(), hu.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(df, hf.data(), hf.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess))
+        rc = MG_EHIP;
+    if (!rc) {
+        p.image = (const unsigned char *)dimg;
+        if constexpr (sizeof(T) == 8) p.ainv = h->cinv64[adj];
+        else p.ainv = h->cinv32[adj];
+        if (launch_tail_cycle<T>(p, (T *)du, (const T *)df, nb, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess ||
+            hipMemcpy(hu.data(), du, hu.size() * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = MG_EHIP;
+    }
+    if (dimg) (void)hipFree(dimg);
+    if (du) (void)hipFree(du);
+    if (df) (void)hipFree(df);
+    if (rc) return rc;
+    std::vector<T> m((size_t)nb * nu);
+    for (int k = 0; k < nb; ++k)
+        for (int i = 0; i < nu; ++i) m[(size_t)k * nu + i] = hu[(size_t)k * nn + node(i)];
+    if (hipMalloc(out, m.size() * sizeof(T)) != hipSuccess) return MG_ENOMEM;
+    if (hipMemcpy(*out, m.data(), m.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return MG_EHIP;
+    return MG_OK;
 }
 
 int build_tail(mg_handle *h)
@@ -1086,10 +1152,37 @@ int build_tail(mg_handle *h)
         lt = l;
     }
     if (lt < 0) return MG_OK;
+    // the largest level below the finest (zero boundary values) and above the
+    // coarsest with at most TAIL_MAP_MAX unknowns runs its sub-cycle as a map
+    int lm = -1;
+    const char *envm = std::getenv("TWMG_NO_TAIL_MAP");
+    if (!(envm && envm[0] == '1'))
+        for (int l = nl - 2; l >= std::max(lt, 1); --l) {
+            long long nu = 1;
+            for (int a = 0; a < h->grid.dim; ++a) nu *= h->lev[l].d.n[a] - 1;
+            if (nu > TAIL_MAP_MAX) break;
+            lm = l;
+        }
+    if (lm >= 0) {
+        int rc = MG_OK;
+        for (int adj = 0; adj < 2 && !rc; ++adj) {
+            rc = build_tail_map<double>(h, lm, adj, &h->tail_map[0][adj]);
+            if (!rc) rc = build_tail_map<float>(h, lm, adj, &h->tail_map[1][adj]);
+        }
+        if (rc) return rc;
+        h->tail_map_lv = lm;
+    }
     for (int adj = 0; adj < 2; ++adj) {
         std::vector<unsigned char> i64, i32;
         tail_image<double>(h, lt, adj, i64, h->tail64[adj]);
         tail_image<float>(h, lt, adj, i32, h->tail32[adj]);
+        if (lm >= 0) {
+            long long nu = 1;
+            for (int a = 0; a < h->grid.dim; ++a) nu *= h->lev[lm].d.n[a] - 1;
+            h->tail64[adj].map = (const double *)h->tail_map[0][adj];
+            h->tail32[adj].map = (const float *)h->tail_map[1][adj];
+            h->tail64[adj].map_nu = h->tail32[adj].map_nu = (int)nu;
+        }
         const std::vector<unsigned char> *src[2] = {&i64, &i32};
         for (int k = 0; k < 2; ++k) {
             void *p = nullptr;

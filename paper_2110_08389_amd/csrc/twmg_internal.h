@@ -200,7 +200,11 @@ constexpr int TAIL_NT = NT / 2;    // lanes of the coarse-level workgroup
 constexpr int TAIL_SHORT_CH = 4;
 constexpr int TAIL_SHORT_MAXN = 32; // levels with at most this many cells per axis
 
-enum TailOpKind : uint8_t { TO_SWEEP = 0, TO_CHECKER = 1, TO_RESTRICT = 2, TO_PROLONG = 3, TO_SOLVE = 4 };
+// TO_MAP: the whole sub-cycle of a level applied as its precomputed affine
+// map (TailPlan::map), in place of the operations it stands for
+enum TailOpKind : uint8_t { TO_SWEEP = 0, TO_CHECKER = 1, TO_RESTRICT = 2, TO_PROLONG = 3, TO_SOLVE = 4, TO_MAP = 5 };
+// largest number of unknowns of a level whose sub-cycle is applied as a map
+constexpr int TAIL_MAP_MAX = 64;
 struct TailOp {
     uint8_t kind;   // TailOpKind
     uint8_t lv;     // level, counted from the first level of the tail
@@ -231,6 +235,12 @@ template <typename T> struct TailPlan {
     int dim = 2;
     long long nn0 = 0;                    // nodes of the first tail level (batch stride)
     const T *ainv = nullptr;              // coarsest-level inverse (global memory)
+    // TO_MAP: the sub-cycle of one level (map_nu <= TAIL_MAP_MAX interior
+    // unknowns, numbered x fastest) as u_out = U u_in + F f, stored input
+    // major: map[k * map_nu + i] is U[i][k] for k < map_nu and F[i][k - map_nu]
+    // above (global memory)
+    const T *map = nullptr;
+    int map_nu = 0;
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------

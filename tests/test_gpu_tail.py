@@ -2,7 +2,11 @@
 problem) against the per-level kernels of the same library: with
 TWMG_NO_TAIL=1 every level uses the per-level launches.  Both paths evaluate
 the same per-point formulas, so cycles agree to rounding (1e-13 relative);
-the oracle parity of both paths is covered by test_gpu_parity."""
+the oracle parity of both paths is covered by test_gpu_parity.  Inside the
+coarse-level kernel the sub-cycle of the largest level with at most 64
+unknowns runs as its precomputed affine map (TWMG_NO_TAIL_MAP=1 runs its
+operations instead); the map is exact up to rounding, so the same bound
+holds."""
 import os
 
 import numpy as np
@@ -15,18 +19,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def make(n, kind, c, sm, notail, **kw):
+def make(n, kind, c, sm, notail, nomap=False, **kw):
     import paper_2110_08389_amd as pkg
 
-    old = os.environ.get("TWMG_NO_TAIL")
+    saved = {k: os.environ.get(k) for k in ("TWMG_NO_TAIL", "TWMG_NO_TAIL_MAP")}
     os.environ["TWMG_NO_TAIL"] = "1" if notail else "0"
+    os.environ["TWMG_NO_TAIL_MAP"] = "1" if nomap else "0"
     try:
         return pkg.Solver(n, stretch=(kind, c), smoother=sm, device=torch.device("cuda", 0), **kw)
     finally:
-        if old is None:
-            del os.environ["TWMG_NO_TAIL"]
-        else:
-            os.environ["TWMG_NO_TAIL"] = old
+        for k, v in saved.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
 CASES = [([64, 64], "tanh_wall", 3.0, "tweed", {}),
@@ -92,3 +98,21 @@ def test_tail_follows_option_changes():
         b.vcycle(ub, f)
         torch.cuda.synchronize()
         assert rel_inf(ua.cpu().numpy(), ub.cpu().numpy()) < 1e-13, opts
+
+
+@pytest.mark.parametrize("n,kind,c,sm,kw", [([256, 256], "sinh_centre", 4.0, "wireframe", {"gamma": 2}),
+                                            ([64, 64], "tanh_wall", 3.0, "tweed", {}),
+                                            ([32, 32, 32], "tanh_wall", 2.5, "tweed", {"gamma": 2})])
+def test_tail_map_matches_its_operations(n, kind, c, sm, kw):
+    """The sub-cycle map against the operations it replaces; with gamma = 2
+    the mapped level is also entered with a nonzero u (second visit)."""
+    a = make(n, kind, c, sm, False, **kw)
+    b = make(n, kind, c, sm, False, nomap=True, **kw)
+    shape = tuple(a.shape())
+    f = torch.tensor(inputs.uniform(shape, 14), device=a.device)
+    ua, ub = torch.zeros_like(f), torch.zeros_like(f)
+    for _ in range(3):
+        a.vcycle(ua, f)
+        b.vcycle(ub, f)
+    torch.cuda.synchronize()
+    assert rel_inf(ua.cpu().numpy(), ub.cpu().numpy()) < 1e-13
