@@ -1326,11 +1326,21 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
             T acc = 0;
             long long slot = 0;
             if (i < nu) {
+                // unknown k at node (ik, jk, lk), x fastest; the map's loads
+                // are independent of the sum, so unrolling keeps many in flight
+                int ik = 1, jk = 1, lk = 1;
+#pragma unroll 16
                 for (int k = 0; k < nu; ++k) {
-                    const int ik = 1 + k % nx, jk = 1 + (k / nx) % ny, lk = DIM == 3 ? 1 + k / (nx * ny) : 0;
                     const long long pk = ik + jk * d.st[1] + (DIM == 3 ? lk * d.st[2] : 0);
                     acc += P.map[(long long)k * nu + i] * us[pk];
                     acc += P.map[(long long)(nu + k) * nu + i] * fs[pk];
+                    if (++ik > nx) {
+                        ik = 1;
+                        if (++jk > ny) {
+                            jk = 1;
+                            ++lk;
+                        }
+                    }
                 }
                 const int ii = 1 + i % nx, ji = 1 + (i / nx) % ny, li = DIM == 3 ? 1 + i / (nx * ny) : 0;
                 slot = ii + ji * d.st[1] + (DIM == 3 ? li * d.st[2] : 0);

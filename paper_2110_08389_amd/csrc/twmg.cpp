@@ -804,7 +804,7 @@ struct mg_handle {
     TailPlan<double> tail64[2];
     TailPlan<float> tail32[2];
     int tail_key[4] = {-1, -1, -1, -1}; // checker, nu1, nu2, gamma the images were built for
-    int tail_map_lv = -1;  // level whose sub-cycle the coarse-level kernel applies as a map (-1: none)
+    int tail_map_lv[2] = {-1, -1}; // [FP64, FP32] level whose sub-cycle the coarse-level kernel applies as a map
     void *tail_map[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // [FP64, FP32][forward, transposed]
 };
 
@@ -947,14 +947,14 @@ int motif_slots(int smoother, int dim, int *m0, int *m1, bool *checker)
 // on the cycle options, so the images are rebuilt when those change.
 // TWMG_NO_TAIL=1 keeps every level on the per-level kernels.
 // ---------------------------------------------------------------------------
-void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, std::vector<TailOp> &ops)
+void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, int map_lv, std::vector<TailOp> &ops)
 {
     const uint8_t rel = (uint8_t)(lv - lt);
     if (lv == h->nlev - 1) {
         ops.push_back(TailOp{TO_SOLVE, rel, 0, 0});
         return;
     }
-    if (lv == h->tail_map_lv) {
+    if (lv == map_lv) {
         ops.push_back(TailOp{TO_MAP, rel, 0, 0});
         return;
     }
@@ -971,7 +971,7 @@ void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, std::vector<TailO
     };
     for (int k = 0; k < h->opt.nu1; ++k) relax();
     ops.push_back(TailOp{TO_RESTRICT, rel, 0, 0});
-    for (int g = 0; g < h->opt.gamma; ++g) tail_ops_rec(h, lt, lv + 1, adj, ops);
+    for (int g = 0; g < h->opt.gamma; ++g) tail_ops_rec(h, lt, lv + 1, adj, map_lv, ops);
     ops.push_back(TailOp{TO_PROLONG, rel, 0, 0});
     for (int k = 0; k < h->opt.nu2; ++k) relax();
 }
@@ -996,7 +996,7 @@ size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char
 {
     const int nt = h->nlev - lt, dim = h->grid.dim;
     std::vector<TailOp> ops;
-    tail_ops_rec(h, lt, lt, adj, ops);
+    tail_ops_rec(h, lt, lt, adj, h->tail_map_lv[sizeof(T) == 8 ? 0 : 1], ops);
     ImageBuf I;
     std::vector<TailLevel> tl(nt);
     std::memset(tl.data(), 0, tl.size() * sizeof(TailLevel));
@@ -1072,14 +1072,14 @@ void free_tail(mg_handle *h)
             p = nullptr;
         }
     h->tail_lv = -1;
-    h->tail_map_lv = -1;
+    h->tail_map_lv[0] = h->tail_map_lv[1] = -1;
 }
 
 // The sub-cycle of level lm (zero boundary values, nu <= TAIL_MAP_MAX
 // interior unknowns) is linear in the level's u and f: it is computed once by
 // the coarse-level kernel itself, started at lm, on the 2 nu unit vectors as a
 // batch, and stored input-major for TailPlan::map.  lm's operations must be
-// the plain ones (tail_map_lv < 0) while this runs.
+// the plain ones (tail_map_lv < 0 for T) while this runs.
 template <typename T> int build_tail_map(mg_handle *h, int lm, int adj, void **out)
 {
     const Level &L = h->lev[lm];
@@ -1153,35 +1153,41 @@ int build_tail(mg_handle *h)
     }
     if (lt < 0) return MG_OK;
     // the largest level below the finest (zero boundary values) and above the
-    // coarsest with at most TAIL_MAP_MAX unknowns runs its sub-cycle as a map
-    int lm = -1;
+    // coarsest with at most TAIL_MAP_MAX unknowns (FP32: TAIL_MAP_MAX32) runs
+    // its sub-cycle as a map
     const char *envm = std::getenv("TWMG_NO_TAIL_MAP");
-    if (!(envm && envm[0] == '1'))
+    auto unknowns = [&](int l) {
+        long long nu = 1;
+        for (int a = 0; a < h->grid.dim; ++a) nu *= h->lev[l].d.n[a] - 1;
+        return nu;
+    };
+    int lm[2] = {-1, -1};
+    for (int k = 0; k < 2; ++k) {
+        if (envm && envm[0] == '1') break;
         for (int l = nl - 2; l >= std::max(lt, 1); --l) {
-            long long nu = 1;
-            for (int a = 0; a < h->grid.dim; ++a) nu *= h->lev[l].d.n[a] - 1;
-            if (nu > TAIL_MAP_MAX) break;
-            lm = l;
+            if (unknowns(l) > (k == 0 ? TAIL_MAP_MAX : TAIL_MAP_MAX32)) break;
+            lm[k] = l;
         }
-    if (lm >= 0) {
-        int rc = MG_OK;
-        for (int adj = 0; adj < 2 && !rc; ++adj) {
-            rc = build_tail_map<double>(h, lm, adj, &h->tail_map[0][adj]);
-            if (!rc) rc = build_tail_map<float>(h, lm, adj, &h->tail_map[1][adj]);
-        }
-        if (rc) return rc;
-        h->tail_map_lv = lm;
     }
+    for (int adj = 0; adj < 2; ++adj) {
+        int rc = MG_OK;
+        if (lm[0] >= 0) rc = build_tail_map<double>(h, lm[0], adj, &h->tail_map[0][adj]);
+        if (!rc && lm[1] >= 0) rc = build_tail_map<float>(h, lm[1], adj, &h->tail_map[1][adj]);
+        if (rc) return rc;
+    }
+    h->tail_map_lv[0] = lm[0];
+    h->tail_map_lv[1] = lm[1];
     for (int adj = 0; adj < 2; ++adj) {
         std::vector<unsigned char> i64, i32;
         tail_image<double>(h, lt, adj, i64, h->tail64[adj]);
         tail_image<float>(h, lt, adj, i32, h->tail32[adj]);
-        if (lm >= 0) {
-            long long nu = 1;
-            for (int a = 0; a < h->grid.dim; ++a) nu *= h->lev[lm].d.n[a] - 1;
+        if (lm[0] >= 0) {
             h->tail64[adj].map = (const double *)h->tail_map[0][adj];
+            h->tail64[adj].map_nu = (int)unknowns(lm[0]);
+        }
+        if (lm[1] >= 0) {
             h->tail32[adj].map = (const float *)h->tail_map[1][adj];
-            h->tail64[adj].map_nu = h->tail32[adj].map_nu = (int)nu;
+            h->tail32[adj].map_nu = (int)unknowns(lm[1]);
         }
         const std::vector<unsigned char> *src[2] = {&i64, &i32};
         for (int k = 0; k < 2; ++k) {

@@ -3,10 +3,10 @@ problem) against the per-level kernels of the same library: with
 TWMG_NO_TAIL=1 every level uses the per-level launches.  Both paths evaluate
 the same per-point formulas, so cycles agree to rounding (1e-13 relative);
 the oracle parity of both paths is covered by test_gpu_parity.  Inside the
-coarse-level kernel the sub-cycle of the largest level with at most 64
-unknowns runs as its precomputed affine map (TWMG_NO_TAIL_MAP=1 runs its
-operations instead); the map is exact up to rounding, so the same bound
-holds."""
+coarse-level kernel the sub-cycle of the largest level with at most 256
+unknowns (64 in FP32 cycles) runs as its precomputed affine map
+(TWMG_NO_TAIL_MAP=1 runs its operations instead); the map is exact up to
+rounding, so the same bound holds."""
 import os
 
 import numpy as np
