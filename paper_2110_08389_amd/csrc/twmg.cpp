@@ -1153,8 +1153,8 @@ int build_tail(mg_handle *h)
     }
     if (lt < 0) return MG_OK;
     // the largest level below the finest (zero boundary values) and above the
-    // coarsest with at most TAIL_MAP_MAX unknowns (FP32: TAIL_MAP_MAX32) runs
-    // its sub-cycle as a map
+    // coarsest with at most TAIL_MAP_MAX unknowns runs its sub-cycle as a map
+    // (one map per precision, each computed by that precision's kernel)
     const char *envm = std::getenv("TWMG_NO_TAIL_MAP");
     auto unknowns = [&](int l) {
         long long nu = 1;
@@ -1165,7 +1165,7 @@ int build_tail(mg_handle *h)
     for (int k = 0; k < 2; ++k) {
         if (envm && envm[0] == '1') break;
         for (int l = nl - 2; l >= std::max(lt, 1); --l) {
-            if (unknowns(l) > (k == 0 ? TAIL_MAP_MAX : TAIL_MAP_MAX32)) break;
+            if (unknowns(l) > TAIL_MAP_MAX) break;
             lm[k] = l;
         }
     }

@@ -204,10 +204,7 @@ constexpr int TAIL_SHORT_MAXN = 32; // levels with at most this many cells per a
 // map (TailPlan::map), in place of the operations it stands for
 enum TailOpKind : uint8_t { TO_SWEEP = 0, TO_CHECKER = 1, TO_RESTRICT = 2, TO_PROLONG = 3, TO_SOLVE = 4, TO_MAP = 5 };
 // largest number of unknowns of a level whose sub-cycle is applied as a map
-// (FP32 cycles: a smaller level, whose map's shorter sums keep the cycle's
-// FP32 rounding close to that of the operations it replaces)
 constexpr int TAIL_MAP_MAX = 256;
-constexpr int TAIL_MAP_MAX32 = 64;
 static_assert(TAIL_MAP_MAX <= TAIL_NT, "one lane per unknown of a mapped level");
 struct TailOp {
     uint8_t kind;   // TailOpKind

@@ -4,9 +4,12 @@ TWMG_NO_TAIL=1 every level uses the per-level launches.  Both paths evaluate
 the same per-point formulas, so cycles agree to rounding (1e-13 relative);
 the oracle parity of both paths is covered by test_gpu_parity.  Inside the
 coarse-level kernel the sub-cycle of the largest level with at most 256
-unknowns (64 in FP32 cycles) runs as its precomputed affine map
-(TWMG_NO_TAIL_MAP=1 runs its operations instead); the map is exact up to
-rounding, so the same bound holds."""
+unknowns runs as its precomputed affine map (TWMG_NO_TAIL_MAP=1 runs its
+operations instead); the map is exact up to rounding, so the same bound
+holds in FP64.  In FP32 cycles the map's sums (up to 450 terms) round
+differently from the operations they replace, by FP32 amounts: a refined
+solve takes the same cycles to the same solution, and its FP64 residual
+history agrees to 1e-3 relative."""
 import os
 
 import numpy as np
@@ -81,7 +84,7 @@ def test_tail_full_solve(prec):
     assert sa["status"] == 0 and sb["status"] == 0 and sa["cycles"] == sb["cycles"]
     tol = 1e-12 if prec == "fp64" else 1e-6
     assert rel_inf(ua.cpu().numpy(), ub.cpu().numpy()) < tol
-    np.testing.assert_allclose(sa["history"], sb["history"], rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(sa["history"], sb["history"], rtol=1e-6 if prec == "fp64" else 1e-3, atol=1e-12)
 
 
 def test_tail_follows_option_changes():
