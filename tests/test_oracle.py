@@ -47,6 +47,23 @@ def test_coords_clustering_direction():
     assert 0.8 * np.cosh(3.0) ** 2 < h.max() / h.min() < 1.2 * np.cosh(3.0) ** 2
 
 
+@pytest.mark.parametrize("b", [1.0, 2.5, 4.0])
+def test_sinh_centre_spacing_closed_form(b):
+    """Centre clustering x(s) = 1/2 + sinh(b(2s-1))/(2 sinh b), s = i/n: the
+    derivative dx/ds = b cosh(b(2s-1))/sinh b fixes the spacing, so the end
+    spacing is b coth(b)/n, the centre spacing b/(n sinh b), and their ratio
+    cosh b (27.3 at b = 4).  A map with b scaled (say b/2, ratio cosh 2) or with
+    the wrong normalisation fails these to far more than the O(1/n^2)
+    discretisation error allowed here."""
+    n = 4096
+    h = np.diff(O.coords("sinh_centre", b, n))
+    assert abs(h.max() / h.min() / np.cosh(b) - 1) < 1e-3
+    # the ends are the widest cells, the centre the narrowest
+    assert h.argmax() in (0, n - 1) and h.argmin() in (n // 2 - 1, n // 2)
+    assert abs(h[0] * n / (b / np.tanh(b)) - 1) < 1e-3
+    assert abs(h[n // 2] * n / (b / np.sinh(b)) - 1) < 1e-3
+
+
 def test_uniform_coefficients_closed_form():
     """Section 2: on an unstretched grid W = E = 1/dx^2."""
     x = O.coords("uniform", 0, 10, 2.5)
