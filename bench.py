@@ -5,7 +5,7 @@ smoother half-sweep's achieved HBM bandwidth against the MI355X roofline.
 One step = one mg_solve from u = 0 to ||f - L u||_inf / ||f||_inf < 1e-10 on
 inputs already resident in HBM.  Prints ONE JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--extras]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-refinement] [--extras]
 """
 import argparse
 import json
@@ -26,34 +26,103 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # (8 B x 1/2), u written at the relaxed colour (8 B x 1/2)
 HALF_SWEEP_BYTES_PER_UNKNOWN = 12.0
 PMC_FILE = os.path.join(ROOT, "profiles", "tweed_halfsweep_4097_pmc.json")
+# the sources of that kernel: the counter summary is valid for them only
+PMC_SOURCES = ["paper_2110_08389_amd/csrc/kernels.hip", "paper_2110_08389_amd/csrc/sweep_core.h",
+               "paper_2110_08389_amd/csrc/twmg_internal.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """CPU model and the cores this process may use (the oracle's host)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "cpus_online": os.cpu_count(), "cpus_usable": usable}
+
+
 def cpu_baseline(f, cycles_gpu):
-    """The FP64 oracle on this host, single-threaded: the first three V(2,2)
-    cycles at full size from u = 0 (a bounded sample of about 15 s), their
-    mean time per cycle scaled to the cycle count the GPU solve needs."""
+    """The FP64 oracle on this host: a whole solve of the timed workload (from
+    u = 0 until the relative defect is below 1e-10, every cycle and defect
+    norm), first on one thread, then on every usable core (its parallel loops
+    give the same bits; the cycle counts are checked equal)."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     import oracle as O
 
     x = O.coords(*STRETCH, N_CELLS)
     H = O.Hierarchy([x, x], "tweed")
-    ncyc = 3
-    u = np.zeros_like(f)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for _ in range(ncyc):
-            u = H.cycle(u, f, 2, 2)
-        dt = (time.perf_counter() - t0) / ncyc
     unknowns = (N_CELLS - 1) ** 2
-    return {"value": unknowns / (dt * cycles_gpu), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {ncyc} V(2,2) tweed cycles at 4097^2 from u=0 ({ncyc * dt:.1f} s on one thread, "
-                      f"{dt:.2f} s per cycle), scaled to the {cycles_gpu} cycles the solve takes"}
+    info = host_info()
+    old = O.get_threads()
+    legs = {}
+    try:
+        for nt in (1, info["cpus_usable"] or 1):
+            O.set_threads(nt)
+            t0 = time.perf_counter()
+            _, k, hist, sto = H.solve(np.zeros_like(f), f, tol=TOL)
+            dt = time.perf_counter() - t0
+            legs[nt] = (dt, k, sto, float(hist[-1]) if k else 0.0)
+            log(f"oracle solve on {nt} thread(s): {k} cycles, {dt:.1f} s")
+    finally:
+        O.set_threads(old)
+    dt1, k1, st1, rel1 = legs[1]
+    nall = max(legs)
+    dtn, kn, _, _ = legs[nall]
+    if kn != k1:
+        log(f"oracle: {k1} cycles on one thread but {kn} on {nall}")
+    return {"value": unknowns / dt1, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"one whole oracle solve of the 4097^2 workload from u=0 to 1e-10 ({k1} V(2,2) cycles, "
+                      f"status {st1}, rel residual {rel1:.2e}; the GPU solve takes {cycles_gpu}): {dt1:.1f} s "
+                      f"on one thread",
+            "all_cores": {"value": unknowns / dtn, "cores": nall, "seconds": dtn, "cycles": kn,
+                          "same_cycles_as_one_thread": kn == k1},
+            "host": info}
+
+
+def refinement_record(pkg, inputs, torch, dev, reps=3):
+    """The centre-clustered 2049^2 workload (sinh, b = 4), wireframe W(2,2) to
+    1e-10: plain FP64 against FP32 cycles inside FP64 refinement on the same
+    GPU, with the refined solution's error against the FP64 one (whose
+    iterates match the FP64 oracle's to 1e-12 in the parity tests)."""
+    n = 2048
+    f = torch.tensor(inputs.normal((n + 1, n + 1), 1002), device=dev)
+    rec = {"workload": "2D Poisson 2049^2 nodes, sinh centre clustering b=4 both axes, wireframe W(2,2), "
+                       "f ~ N(0,1) seed 1002, tol 1e-10"}
+    sol = {}
+    for prec in ("fp64", "fp32_ir"):
+        s = pkg.Solver([n, n], stretch=("sinh_centre", 4.0), smoother="wireframe", gamma=2, precision=prec,
+                       max_cycles=60, device=dev)
+        ms, st, u = timed_solve(s, f, torch, reps=reps, keep=True)
+        sol[prec] = u
+        rec[prec] = {"ms": ms, "cycles": st["cycles"], "status": st["status"], "rel_res": st["rel_res"],
+                     "unknowns_per_s": (n - 1) ** 2 / (ms * 1e-3)}
+        del s
+    a, b = sol["fp64"], sol["fp32_ir"]
+    rec["fp32_ir"]["rel_error_vs_fp64"] = float((b - a).abs().max() / a.abs().max())
+    rec["fp32_ir_speedup"] = rec["fp64"]["ms"] / rec["fp32_ir"]["ms"]
+    return rec
+
+
+def source_sha(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -64,6 +133,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     ap.add_argument("--sweep-reps", type=int, default=20)
+    ap.add_argument("--no-refinement", action="store_true",
+                    help="skip the FP64 vs FP32-refinement record of the 2049^2 wireframe workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -138,12 +209,27 @@ def main():
     half_ms = ev0.elapsed_time(ev1) / args.sweep_reps
     alg_bytes = HALF_SWEEP_BYTES_PER_UNKNOWN * unknowns
     achieved = alg_bytes / (half_ms * 1e-3) / 1e9
+    # HBM traffic of that kernel from the committed rocprofv3 counter summary,
+    # valid only for the kernel sources it was taken with
     traffic = None
     if os.path.exists(PMC_FILE):
         try:
-            traffic = json.load(open(PMC_FILE)).get("bytes_per_launch")
+            pmc = json.load(open(PMC_FILE))
+            if pmc.get("source_sha") == source_sha(PMC_SOURCES):
+                traffic = pmc.get("bytes_per_launch")
+            else:
+                log("roofline.traffic: the counter summary predates the current kernel sources; reported as null")
         except Exception:  # a malformed profile summary leaves traffic unknown
             traffic = None
+    # per-cycle convergence factor of the solve, beside the paper's two-grid
+    # figure for tweed with nu = 4 on the tanh c = 3 grid (Table 3)
+    hist = st["history"]
+    factor = hist[-1] ** (1.0 / len(hist)) if hist else None
+    ratios = [hist[0]] + [hist[k] / hist[k - 1] for k in range(1, len(hist))] if hist else []
+    refine = None
+    if not args.no_refinement:
+        log("refinement record (2049^2 wireframe W(2,2)) ...")
+        refine = refinement_record(pkg, inputs, torch, dev)
 
     out = {
         "metric": "unknowns/s solved to 1e-10 rel. residual (tweed MG, 4097^2); sweep HBM GB/s",
@@ -161,7 +247,12 @@ def main():
         "config": {"workload": "2D Poisson 4097^2 nodes, tanh wall clustering g=3 both axes, tweed V(2,2), "
                                "full weighting, bilinear prolongation, coarsest 3x3, FP64, tol 1e-10",
                    "cycles": st["cycles"], "rel_res": st["rel_res"], "setup_s": round(setup_s, 3),
-                   "half_sweep_ms": half_ms},
+                   "half_sweep_ms": half_ms,
+                   "convergence": {"mean_factor_per_cycle": factor, "per_cycle": ratios,
+                                   "paper_two_grid_rho_tweed_tanh3_nu4": 0.0204,
+                                   "note": "paper Table 3 (two-grid, 65^2); the V-cycle factor on 4097^2 is "
+                                           "measured on the defect max-norm"}},
+        **({"fp32_refinement": refine} if refine else {}),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_block_sweep<double,2,256> (finest-level tweed red half-sweep)",
@@ -176,7 +267,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def timed_solve(s, f, torch, reps=3, bc=None, tol=TOL):
+def timed_solve(s, f, torch, reps=3, bc=None, tol=TOL, keep=False):
     u = s.zeros()
     s.solve(f, bc, tol=tol, u=u)
     torch.cuda.synchronize()
@@ -184,7 +275,8 @@ def timed_solve(s, f, torch, reps=3, bc=None, tol=TOL):
     for _ in range(reps):
         _, st = s.solve(f, bc, tol=tol, u=u)
     torch.cuda.synchronize()
-    return 1e3 * (time.perf_counter() - t0) / reps, st
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    return (ms, st, u) if keep else (ms, st)
 
 
 def extras(pkg, inputs, torch, dev):

@@ -90,7 +90,8 @@ typedef struct {
 typedef struct {
     int cycles;       /* cycles (refinement steps) done                               */
     int status;       /* MG_OK, MG_ENOTCONV or MG_EDIVERGED                           */
-    double rel_res;   /* final ||f - L u||_inf / ||f - L u_0||_inf (interior nodes)   */
+    double rel_res;   /* final ||f - L u||_inf / ||f - L u_0||_inf (interior nodes;   *
+                       * each problem against its own, the largest over the batch)   */
     double res0;      /* ||f - L u_0||_inf (largest over the batch)                   */
     double *history;  /* optional host array: rel_res after each cycle                */
     int history_cap;  /* its capacity                                                 */
@@ -104,7 +105,11 @@ typedef struct mg_handle mg_handle;
  * every level in FP64 and FP32 for the operator and its transpose, the
  * smoother block tables (Section 3 motifs), and uploads them.  stream is a
  * hipStream_t (NULL = default stream).  Returns MG_EINVAL for odd or too small
- * n, unknown kinds, dim not 2/3, batch < 1; *out is set only on success. */
+ * n (or n above 32000), unknown kinds, dim not 2/3, batch < 1;
+ * MG_EUNSUPPORTED when one problem's array (in the device layout, which holds
+ * up to twice the nodes) would reach 2^31 entries -- the kernels address a
+ * problem with 32-bit offsets -- or for a smoother this build does not
+ * provide in that dimension; *out is set only on success. */
 int mg_setup(const mg_grid *grid, const mg_stretching *stretch, const mg_options *opt, void *stream,
              mg_handle **out);
 void mg_destroy(mg_handle *h);
@@ -133,8 +138,11 @@ int mg_vcycle(mg_handle *h, double *u, const double *f);
 
 /* Solve: u's boundary nodes are set from bc (if bc != NULL; else u's own
  * boundary values are used), its interior set to 0 (unless MG_INITIAL_GUESS),
- * then cycles run until ||f - L u||_inf / ||f - L u_0||_inf < tol for every batch
- * problem (Section 4 stopping rule; the maximum over the batch is used).
+ * then cycles run until ||f_b - L u_b||_inf / ||f_b - L u_b,0||_inf < tol for
+ * every batch problem b (Section 4 stopping rule, each problem measured
+ * against its own initial defect; a problem whose initial defect is zero is
+ * already solved and is left out).  stats->rel_res is the largest of these
+ * ratios and stats->res0 the largest initial defect.
  * With precision MG_FP32_IR each step is r = f - A u in FP64, one FP32 cycle
  * on A e = r from e = 0, u += e in FP64.  Returns MG_OK, MG_ENOTCONV (u holds
  * the last iterate) or MG_EDIVERGED.  stats may be NULL. */
@@ -143,15 +151,24 @@ int mg_solve(mg_handle *h, double *u, const double *f, const double *bc, double 
 /* Adjoint solve A_II^T lam = w_I (interior), lam = 0 on the boundary, by the
  * same cycle applied to the transposed operator with the colour order of every
  * block sweep reversed, so that the adjoint cycle is the transpose of the
- * forward one.  w is a full node array; only its interior is read. */
+ * forward one.  w is a full node array; only its interior is read.  An
+ * extension of the method for differentiation: the paper defines no adjoint,
+ * so no passage is cited (A is the operator of problem (DP), Section 2).  The
+ * stopping rule and return codes are those of mg_solve. */
 int mg_solve_adjoint(mg_handle *h, double *lam, const double *w, double tol, mg_stats *stats);
 
 /* Gradient of L = sum(w * u) with respect to the Dirichlet data g, given the
  * adjoint solution lam:  grad_g = w_B - A_IB^T lam on boundary nodes, 0 on
- * interior nodes (the gradient with respect to f is lam itself). */
+ * interior nodes (the gradient with respect to f is lam itself).  An extension
+ * for differentiation with no passage in the paper: A_IB is the part of the
+ * operator of problem (DP), Section 2, that couples interior nodes to the
+ * boundary data.  Asynchronous; lam, w and grad_bc are full node arrays
+ * (grad_bc is written at every node). */
 int mg_bc_grad(mg_handle *h, const double *lam, const double *w, double *grad_bc);
 
-/* ||f - L u||_inf over interior nodes (maximum over the batch), synchronous. */
+/* ||f - L u||_inf over interior nodes, the defect norm of the stopping rule of
+ * Section 4 (the maximum over the batch problems); synchronous, *out_inf is a
+ * host pointer. */
 int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out_inf);
 
 /* Kernel-level entry points on level lv (arrays of that level's shape):

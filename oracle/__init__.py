@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2 -ffp-contract=off: no FMA contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -58,6 +58,9 @@ def lib():
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
         L.orc_coords.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, dp]
         L.orc_coefs.argtypes = [C.c_int, dp, dp, dp]
         L.orc_create.argtypes = [C.c_int, ip, C.POINTER(dp), C.c_int, C.c_int, C.c_int]
@@ -96,6 +99,16 @@ def _dp(a: np.ndarray):
 def _ip(a: np.ndarray):
     assert a.dtype == np.int32 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops (same-colour blocks, node
+    loops); the results are bitwise identical for every count."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def coords(kind, param: float, n: int, L: float = 1.0) -> np.ndarray:

@@ -1,7 +1,7 @@
 /*
  * twmg oracle -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded FP64 CPU implementation of geometric multigrid
+ * A plain, slow FP64 CPU implementation of geometric multigrid
  * with tweed / wireframe / checkerboard / zebra block Gauss-Seidel smoothing for
  * the nonuniform-grid Poisson problem of Bewley, Mashayek, Cavaglieri & Luchini,
  * "Tweed and wireframe: accelerated relaxation algorithms for multigrid solution
@@ -13,6 +13,14 @@
  *
  * Everything is double precision.  Build with -O2 -ffp-contract=off so that the
  * arithmetic is exactly the order written here.
+ *
+ * Threads (OpenMP, orc_set_threads): the only parallel loops are over the
+ * blocks of one colour inside a half-sweep (uncoupled: each reads the other
+ * colour and writes only its own points) and over the nodes of the operator,
+ * defect, transfer and norm loops (each output written by one iteration; the
+ * maximum is exact in any order).  Every value is computed by the same
+ * expression in the same order whatever the thread count, so the results are
+ * bitwise identical to one thread.
  *
  * Conventions (readings of the paper that it leaves open are marked READING):
  *  - nodes are 0-based, i = 0..n (n = number of cells on that axis); interior
@@ -33,8 +41,13 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_MAXLEV 32
+
+/* number of OpenMP threads of the parallel loops (1 = the plain serial order) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* smoother kinds */
 enum { ORC_TWEED = 0, ORC_WIREFRAME = 1, ORC_CHECKER = 2, ORC_ZEBRA_X = 3, ORC_ZEBRA_Y = 4,
@@ -535,6 +548,7 @@ static double pt_diag(const orc_mg *M, const orc_level *L, long q)
 static int *block_ids(const orc_level *L, int slot)
 {
     int *bid = (int *)malloc(sizeof(int) * L->nn);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < L->nn; ++p) bid[p] = -1;
     for (int b = 0; b < L->nblk[slot]; ++b)
         for (int t = L->bstart[slot][b]; t < L->bstart[slot][b + 1]; ++t) bid[L->bpts[slot][t]] = b;
@@ -628,6 +642,7 @@ static int solve_block(const orc_mg *M, const orc_level *L, int slot, const int 
 /* out_p = (L u)_p at interior p (Section 2, problem DP); boundary entries 0. */
 static void apply_op(const orc_mg *M, const orc_level *L, const double *u, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < L->nn; ++p) {
         int c[3];
         ncoord(L, p, c);
@@ -642,6 +657,7 @@ static void apply_op(const orc_mg *M, const orc_level *L, const double *u, doubl
 static void residual(const orc_mg *M, const orc_level *L, const double *u, const double *f, double *d)
 {
     apply_op(M, L, u, d);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < L->nn; ++p) {
         int c[3];
         ncoord(L, p, c);
@@ -656,6 +672,7 @@ static void residual(const orc_mg *M, const orc_level *L, const double *u, const
 static void restrict_op(int dim, const orc_level *F, const orc_level *Cl, const double *d, double *fc, int half)
 {
     static const double w3[3] = { 0.25, 0.5, 0.25 };
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < Cl->nn; ++q) {
         int c[3];
         ncoord(Cl, q, c);
@@ -683,6 +700,7 @@ static void restrict_op(int dim, const orc_level *F, const orc_level *Cl, const 
  * interior nodes (step 5). */
 static void prolong_add(int dim, const orc_level *F, const orc_level *Cl, const double *ec, double *uf)
 {
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < F->nn; ++p) {
         int c[3];
         ncoord(F, p, c);
@@ -925,19 +943,27 @@ static int sweep(const orc_mg *M, const orc_level *L, int slot, double *u, const
 {
     int *bid = block_ids(L, slot);
     size_t mb = max_block(L, slot);
-    double *work = (double *)malloc(sizeof(double) * (dense ? mb * mb + mb : 12 * mb + 8));
+    const size_t wsz = dense ? mb * mb + mb : 12 * mb + 8;
+    const int nb = L->nblk[slot];
     int rc = 0;
     for (int pass = 0; pass < 2 && !rc; ++pass) {
         int colour = M->transpose ? 1 - pass : pass;
-        for (int t = 0; t < L->nblk[slot] && !rc; ++t) {
-            int b = order ? L->nblk[slot] - 1 - t : t;
-            if (L->bcolour[slot][b] != colour) continue;
-            rc = solve_block(M, L, slot, bid, b, u, f, dense, work);
+        /* the blocks of one colour are uncoupled: any order (and any split
+         * over threads) gives the same values */
+#pragma omp parallel reduction(| : rc)
+        {
+            double *work = (double *)malloc(sizeof(double) * wsz);
+#pragma omp for schedule(dynamic, 8)
+            for (int t = 0; t < nb; ++t) {
+                int b = order ? nb - 1 - t : t;
+                if (L->bcolour[slot][b] != colour || rc) continue;
+                if (solve_block(M, L, slot, bid, b, u, f, dense, work)) rc = 1;
+            }
+            free(work);
         }
     }
-    free(work);
     free(bid);
-    return rc;
+    return rc ? -1 : 0;
 }
 
 /* One relaxation of the chosen smoother: for the alternating schemes (ADZ and
@@ -1047,15 +1073,17 @@ int orc_cycle(void *h, double *u, const double *f, int nu1, int nu2, int gamma, 
 static double maxabs_interior(const orc_mg *M, const orc_level *L, const double *d)
 {
     double m = 0.0;
+    int nan = 0;
+#pragma omp parallel for schedule(static) reduction(max : m) reduction(| : nan)
     for (long p = 0; p < L->nn; ++p) {
         int c[3];
         ncoord(L, p, c);
         if (!is_interior(L, M->dim, c)) continue;
         double a = fabs(d[p]);
-        if (a != a) return a; /* NaN propagates */
-        if (a > m) m = a;
+        if (a != a) nan = 1;
+        else if (a > m) m = a;
     }
-    return m;
+    return nan ? NAN : m; /* NaN propagates */
 }
 
 /* Relative infinity-norm of the defect, ||f - L u||_inf over interior nodes. */

@@ -1485,12 +1485,14 @@ __global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const 
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
 }
 
+// per-problem maximum: workgroup b reduces problem b's n partial maxima into out[b]
 __global__ void __launch_bounds__(256) k_max_final(const double *__restrict__ partial, int n, double *__restrict__ out)
 {
+    const double *pb = partial + (long long)blockIdx.x * n;
     double m = 0.0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, partial[k]);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, pb[k]);
     m = block_max(m);
-    if (threadIdx.x == 0) out[0] = m;
+    if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
 
 template <typename T>
@@ -1508,7 +1510,7 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
     } else {
         hipLaunchKernelGGL((k_resnorm<T, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     }
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
+    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(256), 0, s, partial, gx, out);
     return hipGetLastError();
 }
 
@@ -1527,7 +1529,7 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
     } else {
         hipLaunchKernelGGL((k_resnorm<double, 3, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
+    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(256), 0, s, partial, gx, out);
     return hipGetLastError();
 }
 

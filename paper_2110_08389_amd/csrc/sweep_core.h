@@ -88,8 +88,8 @@ template <typename T, int C = CH> struct LaneState {
     bool hp;
 };
 
-// 32-bit slot of node (i, j, l) within one problem's array (every per-problem
-// array is far below 2^31 elements)
+// 32-bit slot of node (i, j, l) within one problem's array (set-up rejects a
+// grid whose per-problem array would reach 2^31 entries)
 __host__ __device__ __forceinline__ int slot32(const Dims &d, int i, int j, int l)
 {
     if (d.layout == LAYOUT_ROW) return i + j * (int)d.st[1] + l * (int)d.st[2];

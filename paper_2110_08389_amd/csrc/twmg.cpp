@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <numeric>
@@ -597,7 +598,7 @@ void pack(std::vector<const HostBlock *> bl, HostTable &t, bool narrow = false)
         // Number them so that consecutive entries of the list (blocks of
         // neighbouring labels, which read the same cache lines) share an XCD
         // and its L2: within each group of 256, entry w goes to XCD w/ceil(size/8).
-        if (!std::getenv("TWMG_NO_XCD_ORDER")) {
+        {
             const int n = (int)(t.wgs.size() - w0), G = 256;
             std::vector<WGDesc> out(n);
             for (int g0 = 0; g0 < n; g0 += G) {
@@ -1034,7 +1035,7 @@ size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char
                 t.nwg[sl][c] = (int)ht.wgs.size();
                 for (const Block &bk : ht.blocks)
                     if (bk.type == BT_RING) t.rings[sl][c] = 1;
-                t.onewave[sl][c] = std::getenv("TWMG_NO_ONEWAVE") ? 0 : 1;
+                t.onewave[sl][c] = 1;
                 for (const WGDesc &w : ht.wgs)
                     if (w.nchunk > 64 || w.nblock > 64) t.onewave[sl][c] = 0;
             }
@@ -1256,6 +1257,9 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         // keeps them in LDS in that layout)
         L.d.layout = (L.d.nn >= SPLIT_MIN_NODES) ? orient : LAYOUT_ROW;
         L.d.bs = L.d.layout == LAYOUT_ROW ? L.d.nn : 2 * L.d.nn;
+        // the kernels address a problem's array with 32-bit slots (the batch
+        // offset is 64-bit): one problem's array must stay below 2^31 entries
+        if (L.d.bs > (long long)INT32_MAX) return MG_EUNSUPPORTED;
         L.g.layout = L.d.layout;
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
@@ -1330,7 +1334,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             const bool tail_size = L.d.nn * 2 * (long long)sizeof(double) <= TAIL_BYTES;
             int nmax = 0;
             for (int a = 0; a < dim; ++a) nmax = std::max(nmax, L.d.n[a]);
-            const bool short_main = dim == 2 && !tail_size && nmax <= SHORT_CH_MAXN && !std::getenv("TWMG_LONG_CHUNKS");
+            const bool short_main = dim == 2 && !tail_size && nmax <= SHORT_CH_MAXN;
             const int maxlen =
                 !tail_size ? (short_main ? SHORT_CH : CH) : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
             std::vector<HostBlock> blocks, short_blocks;
@@ -1340,7 +1344,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             // NT/2 lanes with chunks of SHORT_CH points takes those (shorter
             // chains per lane; a colour with a larger block keeps CH)
             bool short_colour[2] = {maxlen <= SHORT_CH && dim == 2, maxlen <= SHORT_CH && dim == 2};
-            if (dim == 2 && !tail_size && maxlen == CH && !std::getenv("TWMG_LONG_CHUNKS")) {
+            if (dim == 2 && !tail_size && maxlen == CH) {
                 rc = build_blocks(L.g, h->slot_motif[s], short_blocks, SHORT_CH);
                 if (rc == MG_EUNSUPPORTED) short_blocks.clear(); // a block beyond NT chunks
                 else if (rc) return rc;
@@ -1358,7 +1362,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 HostTable &t = L.htab[s][colour];
                 // narrow workgroups for 2D levels too large for the
                 // coarse-level kernel (whose sweeps use NT/2 lanes)
-                const bool narrow = dim == 2 && !tail_size && !std::getenv("TWMG_WIDE_WG");
+                const bool narrow = dim == 2 && !tail_size;
                 pack(sel, t, narrow);
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;
@@ -1440,12 +1444,13 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         if (err) return err;
     }
     {
-        std::vector<double> z(NORM_PARTS + 1, 0.0);
+        // partial maxima, then one defect norm per problem
+        std::vector<double> z(NORM_PARTS + (size_t)grid->batch, 0.0);
         int err = 0;
         h->partial = h->pool.upload(z, err);
         h->normv = h->partial + NORM_PARTS;
         if (err) return err;
-        if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double)));
+        if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double) * grid->batch));
     }
     if ((rc = build_tail(h))) return rc;
     if (!h->pool.host_only) {
@@ -1536,13 +1541,17 @@ template <typename T> int cycle(mg_handle *h, int lv, T *u, const T *f, int adj)
     return MG_OK;
 }
 
-int read_norm(mg_handle *h, double *out)
+// the defect norm of every problem of the batch (out: batch values)
+int read_norms(mg_handle *h, double *out)
 {
-    HIPCHK(hipMemcpyAsync(h->h_norm, h->normv, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    const int B = h->grid.batch;
+    HIPCHK(hipMemcpyAsync(h->h_norm, h->normv, sizeof(double) * B, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    *out = *h->h_norm;
+    for (int b = 0; b < B; ++b) out[b] = h->h_norm[b];
     return MG_OK;
 }
+
+bool finite(double v) { return v == v && !std::isinf(v); }
 
 int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *stats, int adj)
 {
@@ -1552,13 +1561,23 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
     Level &L = h->lev[0];
     const int B = h->grid.batch;
     const bool ir = h->opt.precision == MG_FP32_IR;
-    double d0 = 0, d = 0;
+    // Section 4 stopping rule, per problem: each problem's defect norm is
+    // measured against its own initial one, and the solve stops when the
+    // largest of these ratios is below tol (a problem whose initial defect is
+    // zero is already solved and takes no part)
+    std::vector<double> d0(B), d(B);
     HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
-    if ((rc = read_norm(h, &d0))) return rc;
+    if ((rc = read_norms(h, d0.data()))) return rc;
     int k = 0, status = MG_OK;
-    double rel = 0.0;
-    if (!(d0 == d0) || std::isinf(d0)) status = MG_EDIVERGED;
-    else if (d0 > 0.0) {
+    double rel = 0.0, d0max = 0.0;
+    bool bad0 = false, any = false;
+    for (int b = 0; b < B; ++b) {
+        bad0 = bad0 || !finite(d0[b]);
+        any = any || d0[b] > 0.0;
+        d0max = std::max(d0max, d0[b]);
+    }
+    if (bad0) status = MG_EDIVERGED;
+    else if (any) {
         status = MG_ENOTCONV;
         while (k < h->opt.max_cycles) {
             if (ir) {
@@ -1572,11 +1591,17 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
                 if ((rc = cycle<double>(h, 0, u, f, adj))) return rc;
             }
             HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
-            if ((rc = read_norm(h, &d))) return rc;
-            rel = d / d0;
+            if ((rc = read_norms(h, d.data()))) return rc;
+            rel = 0.0;
+            bool bad = false;
+            for (int b = 0; b < B; ++b) {
+                bad = bad || !finite(d[b]);
+                if (d0[b] > 0.0) rel = std::max(rel, d[b] / d0[b]);
+            }
+            if (bad) rel = std::numeric_limits<double>::infinity();
             if (stats && stats->history && k < stats->history_cap) stats->history[k] = rel;
             ++k;
-            if (!(rel == rel) || std::isinf(rel) || rel > 1e6) {
+            if (!finite(rel) || rel > 1e6) {
                 status = MG_EDIVERGED;
                 break;
             }
@@ -1590,7 +1615,7 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
         stats->cycles = k;
         stats->status = status;
         stats->rel_res = rel;
-        stats->res0 = d0;
+        stats->res0 = d0max;
         stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
@@ -1790,9 +1815,15 @@ int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out
 {
     if (!h || !u || !f || !out_inf) return MG_EINVAL;
     Level &L = h->lev[0];
-    HIPCHK(launch_resnorm<double>(row_dims(L.d), L.c64[0], u, f, h->partial, NORM_PARTS, h->normv, h->grid.batch,
-                                  h->stream));
-    return read_norm(h, out_inf);
+    const int B = h->grid.batch;
+    HIPCHK(launch_resnorm<double>(row_dims(L.d), L.c64[0], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
+    std::vector<double> d(B);
+    const int rc = read_norms(h, d.data());
+    if (rc) return rc;
+    double m = 0.0;
+    for (int b = 0; b < B; ++b) m = (d[b] != d[b] || m != m) ? d[b] + m : std::max(m, d[b]);
+    *out_inf = m;
+    return MG_OK;
 }
 
 int mg_smooth(mg_handle *h, int lv, double *u, const double *f, int nu, int adjoint)

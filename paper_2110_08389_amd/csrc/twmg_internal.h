@@ -272,6 +272,8 @@ hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u,
 template <typename T>
 hipError_t launch_coarse_solve(const Dims &d, const Coef<T> &c, T *u, const T *f, const T *ainv, int nunk, int batch,
                                hipStream_t s);
+// ||f - L u||_inf over the interior of each problem b into out[b] (b < batch);
+// partial holds npart slots of per-workgroup maxima
 template <typename T>
 hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *f, double *partial, int npart,
                           double *out, int batch, hipStream_t s);

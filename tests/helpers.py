@@ -33,3 +33,14 @@ def rel_inf(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rel_inf_scaled(a, b, *inputs):
+    """max |a - b| relative to the largest magnitude among b and the inputs the
+    computation started from: rounding errors scale with the largest values
+    that enter the arithmetic, which for a cycle that cancels most of a large
+    random start are the start's, not the (much smaller) result's."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = max([np.max(np.abs(b))] + [np.max(np.abs(np.asarray(x))) for x in inputs])
+    return float(np.max(np.abs(a - b)) / max(scale, 1e-300))

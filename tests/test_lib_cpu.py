@@ -65,6 +65,15 @@ def test_setup_rejects_bad_input():
     assert host_handle([64, 64, 64], "tanh_wall", 2.0, "wireframe")[0] == pkg.MG_EUNSUPPORTED
 
 
+def test_setup_rejects_arrays_beyond_32bit_offsets():
+    """The kernels address one problem's array with 32-bit offsets: a 1300^3
+    grid (1301^3 = 2.2e9 nodes per array, 17.6 GB in FP64, which would fit in
+    HBM) is refused at set-up, before any table is built, and so is 1290^3
+    (1291^3 = 2.15e9 nodes, just above 2^31 - 1)."""
+    assert host_handle([1300, 1300, 1300], "uniform", 0, "checkerboard")[0] == pkg.MG_EUNSUPPORTED
+    assert host_handle([1290, 1290, 1290], "uniform", 0, "checkerboard")[0] == pkg.MG_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("n,kind,c", [([64, 64], "tanh_wall", 3.0), ([96, 48], "sinh_centre", 4.0),
                                       ([32, 16, 24], "tanh_centre", 1.5)])
 def test_setup_geometry_matches_oracle(n, kind, c):
@@ -132,6 +141,32 @@ def test_kernel_steps_in_device_layout_match_oracle(n, kind, c, sm):
     shape = O.Hierarchy(xs, sm, maxlev=1).shape(0)
     u = inputs.normal(shape, 3)
     f = inputs.normal(shape, 4)
+    for adj in (0, 1):
+        Ho = O.Hierarchy(xs, sm, transpose=bool(adj), maxlev=1)
+        ue = u.copy()
+        assert pkg.capi().mg_debug_host_smooth_layout(h, 0, ue.ctypes.data_as(C.c_void_p),
+                                                      f.ctypes.data_as(C.c_void_p), 1, adj) == 0
+        assert rel_inf(ue, Ho.smooth(u, f, 1)) < 1e-12
+    pkg.capi().mg_destroy(h)
+
+
+def test_kernel_steps_full_size_wireframe_rings_match_oracle():
+    """The 2049^2 centre-clustered grid (sinh, b = 4) of the wireframe
+    workload: its outer rings exceed NT/2 chunks, are built without the
+    plane cuts and run in NT-lane workgroups that address their points in
+    general form -- a path no smaller grid reaches.  The kernel's per-lane
+    steps over the level's own tables and device layout equal the oracle's
+    relaxation, forward and adjoint."""
+    n, kind, c, sm = [2048, 2048], "sinh_centre", 4.0, "wireframe"
+    rc, h = host_handle(n, kind, c, sm)
+    assert rc == 0
+    info = (C.c_int * 6)()
+    assert pkg.capi().mg_debug_table_info(h, 0, 0, 0, info) == 0
+    assert info[3] > 256  # a workgroup holds a block of more than NT/2 chunks
+    xs = [O.coords(kind, c, k) for k in n]
+    shape = (n[1] + 1, n[0] + 1)
+    u = inputs.normal(shape, 5)
+    f = inputs.normal(shape, 6)
     for adj in (0, 1):
         Ho = O.Hierarchy(xs, sm, transpose=bool(adj), maxlev=1)
         ue = u.copy()

@@ -566,3 +566,36 @@ def test_status_not_converged_and_diverged():
     fbad[10, 10] = np.nan
     _, k, _, st = H.solve(np.zeros(H.shape()), fbad, tol=1e-10, max_cycles=5)
     assert st == 2
+
+
+# ----------------------------------------------------------------------------
+# Threads: the parallel loops change no bit of any result
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,kind,c,sm", [([128, 128], "tanh_wall", 3.0, "tweed"),
+                                         ([96, 64], "sinh_centre", 4.0, "wireframe"),
+                                         ([64, 64], "tanh_wall", 2.0, "adz"),
+                                         ([16, 24, 16], "tanh_wall", 2.5, "tweed")])
+def test_threads_bitwise_identical(n, kind, c, sm):
+    """Same-colour blocks are uncoupled and every node loop writes each output
+    once, so a relaxation, a cycle (forward and adjoint) and a solve give the
+    same bits on one thread and on several."""
+    xs = [O.coords(kind, c, k) for k in n]
+    H = O.Hierarchy(xs, sm)
+    Ht = O.Hierarchy(xs, sm, transpose=True)
+    shape = H.shape(0)
+    rng = np.random.default_rng(11)
+    u0 = rng.standard_normal(shape)
+    f = rng.standard_normal(shape)
+    old = O.get_threads()
+    out = []
+    try:
+        for nt in (1, 4):
+            O.set_threads(nt)
+            out.append([H.smooth(u0, f, 2), H.cycle(u0, f), Ht.cycle(u0, f),
+                        H.solve(np.zeros(shape), f, tol=1e-9, max_cycles=30)[0],
+                        np.array([H.resnorm(u0, f)])])
+    finally:
+        O.set_threads(old)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
