@@ -171,6 +171,22 @@ int mg_bc_grad(mg_handle *h, const double *lam, const double *w, double *grad_bc
  * host pointer. */
 int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out_inf);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mg_residual_norm without
+ * any allocation or synchronisation.  Enqueues on the handle's stream the
+ * computation of the maximum over the batch of ||f - L u||_inf (interior
+ * nodes, row-major u and f as for mg_residual_norm) and writes it to
+ * out_dev[0], a DEVICE pointer to one double owned by the caller.  The partial
+ * maxima live in a library-wide device array of 16384 doubles (128 KiB, one
+ * per GPU, resolved at mg_setup and held until the process ends) that every
+ * call on a GPU shares: calls that overlap on one GPU (different streams or
+ * host threads) race and must be ordered by the caller.  Nothing in the array
+ * needs clearing between calls.  Returns MG_EINVAL for null pointers, a
+ * host-only handle, or a batch above 16384 (the array's capacity);
+ * MG_EHIP if the launch fails or the array was never resolved.  Calls no
+ * hipMalloc, hipFree or allocating library routine. */
+int mg_residual_norm_noalloc(mg_handle *h, const double *u, const double *f, double *out_dev);
+
 /* Kernel-level entry points on level lv (arrays of that level's shape):
  * mg_smooth: nu relaxations of the configured smoother (Section 3).
  * mg_residual: d = f - L u at interior nodes, 0 at boundary nodes.

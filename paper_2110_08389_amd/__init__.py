@@ -66,6 +66,7 @@ _SIGS = [
     ("mg_solve_adjoint", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(mg_stats)], C.c_int),
     ("mg_bc_grad", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     ("mg_residual_norm", [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    ("mg_residual_norm_noalloc", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     ("mg_smooth", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
     ("mg_smooth_f32", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
     ("mg_residual", [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
@@ -257,6 +258,15 @@ class Solver:
         out = C.c_double()
         _check(capi().mg_residual_norm(self.h, self._arg(u), self._arg(f), C.byref(out)), "mg_residual_norm")
         return out.value
+
+    def residual_norm_noalloc(self, u, f, out):
+        """mg_residual_norm_noalloc: enqueues the batch's largest defect norm
+        into out[0] (a float64 device tensor); no allocation, no sync."""
+        if out.dtype != self.torch.float64 or out.device != self.device or out.numel() < 1:
+            raise ValueError("out: a float64 device tensor of at least one element")
+        _check(capi().mg_residual_norm_noalloc(self.h, self._arg(u), self._arg(f), _ptr(out)),
+               "mg_residual_norm_noalloc")
+        return out
 
     # -- kernel-level entry points ------------------------------------------------
     def smooth(self, u, f, nu=1, lv=0, adjoint=False):

@@ -5,6 +5,8 @@
 // coalesced rows and enough independent waves per CU.
 #include "sweep_core.h"
 
+#include <mutex>
+
 namespace twmg {
 
 // ---------------------------------------------------------------------------
@@ -1530,6 +1532,65 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
         hipLaunchKernelGGL((k_resnorm<double, 3, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(256), 0, s, partial, gx, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free defect norm: the partial maxima live in a file-scope device
+// array instead of handle-owned memory.  Host code never uses the array's
+// name as an address: scratch_init resolves each device's copy once, with
+// that device current, and the launcher passes that address to the kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[NOALLOC_PARTS];
+constexpr int SCRATCH_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+
+hipError_t scratch_init()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+    return hipSuccess;
+}
+
+hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const double *u, const double *f,
+                                  double *out, int batch, hipStream_t s)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return hipErrorInvalidDevice;
+    double *partial;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        partial = g_scratch_ptr[dev];
+    }
+    if (!partial) return hipErrorNotInitialized;
+    int gx = NOALLOC_PARTS / batch;
+    if (gx < 1) return hipErrorInvalidValue;
+    const int rows = lrow_grid(d);
+    if (gx > rows) gx = rows;
+    // every slot the final reduction reads (gx per problem) is written by the
+    // first kernel: nothing needs clearing
+    if (d.dim == 2) {
+        const int nt = ((d.n[0] + 32) / 32) * ((d.n[1] + 32) / 32);
+        if (gx > nt) gx = nt;
+        hipLaunchKernelGGL((k_resnorm_tile<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
+                           partial);
+    } else {
+        hipLaunchKernelGGL((k_resnorm<double, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
+                           partial);
+    }
+    // one workgroup over all problems' partial maxima: the batch's maximum
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
     return hipGetLastError();
 }
 

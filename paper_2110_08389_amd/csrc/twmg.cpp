@@ -1453,6 +1453,8 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         if (!h->pool.host_only) HIPCHK(hipHostMalloc((void **)&h->h_norm, sizeof(double) * grid->batch));
     }
     if ((rc = build_tail(h))) return rc;
+    // the allocation-free norm's device array on this device (once per device)
+    if (!h->pool.host_only) HIPCHK(scratch_init());
     if (!h->pool.host_only) {
         bool big = false;
         for (int l = 0; l + 1 < h->nlev; ++l)
@@ -1823,6 +1825,15 @@ int mg_residual_norm(mg_handle *h, const double *u, const double *f, double *out
     double m = 0.0;
     for (int b = 0; b < B; ++b) m = (d[b] != d[b] || m != m) ? d[b] + m : std::max(m, d[b]);
     *out_inf = m;
+    return MG_OK;
+}
+
+int mg_residual_norm_noalloc(mg_handle *h, const double *u, const double *f, double *out_dev)
+{
+    if (!h || !u || !f || !out_dev || h->pool.host_only) return MG_EINVAL;
+    if (h->grid.batch > NOALLOC_PARTS) return MG_EINVAL;
+    Level &L = h->lev[0];
+    HIPCHK(launch_resnorm_noalloc(row_dims(L.d), L.c64[0], u, f, out_dev, h->grid.batch, h->stream));
     return MG_OK;
 }
 

@@ -291,4 +291,14 @@ hipError_t launch_tail_cycle(const TailPlan<T> &p, T *u, const T *f, int batch, 
 
 constexpr int NORM_PARTS = 65536; // partial-maximum slots used by launch_resnorm
 
+// Allocation-free defect norm (mg_residual_norm_noalloc): partial maxima in a
+// file-scope device array of NOALLOC_PARTS doubles (128 KiB per device, held
+// until the process ends).  scratch_init resolves the current device's copy
+// (call once per device, that device current); launch_resnorm_noalloc writes
+// the maximum over the batch of ||f - L u||_inf to out[0] (device memory).
+constexpr int NOALLOC_PARTS = 16384;
+hipError_t scratch_init();
+hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const double *u, const double *f,
+                                  double *out, int batch, hipStream_t s);
+
 } // namespace twmg
