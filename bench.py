@@ -115,6 +115,41 @@ def refinement_record(pkg, inputs, torch, dev, reps=3):
     return rec
 
 
+# the other workloads, for profiling runs: (cells per axis, stretching,
+# smoother, gamma, batch, seed, distribution, tol)
+WORKLOADS = {
+    "wireframe2049": ([2048, 2048], ("sinh_centre", 4.0), "wireframe", 2, 1, 1002, "normal", 1e-10),
+    "tweed3d257": ([256, 256, 256], ("tanh_wall", 2.5), "tweed", 1, 1, 1003, "uniform", 1e-9),
+    "batch1025": ([1024, 1024], ("tanh_wall", 2.5), "tweed", 1, 16, 1004, "normal", 1e-10),
+    "adz4097": ([4096, 4096], ("tanh_wall", 3.0), "adz", 1, 1, 1001, "uniform", 1e-10),
+}
+
+
+def profile_workload(pkg, inputs, torch, dev, args):
+    """K solves of one of the other workloads from u = 0 (after W warm-up
+    solves), timed on the host; prints one JSON line with the time per solve."""
+    n, stretch, sm, gamma, B, seed, dist, tol = WORKLOADS[args.workload]
+    s = pkg.Solver(n, stretch=stretch, smoother=sm, gamma=gamma, batch=B, precision=args.precision,
+                   max_cycles=400, device=dev)
+    shape = s.shape(0)
+    f = torch.tensor(inputs.uniform(shape, seed) if dist == "uniform" else inputs.normal(shape, seed), device=dev)
+    u = s.zeros()
+    for _ in range(args.warmup):
+        s.solve(f, tol=tol, u=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = s.solve(f, tol=tol, u=u)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    unknowns = B
+    for k in n:
+        unknowns *= k - 1
+    print(json.dumps({"workload": args.workload, "precision": args.precision, "ms_per_solve": ms,
+                      "cycles": st["cycles"], "status": st["status"], "rel_res": st["rel_res"],
+                      "unknowns_per_s": unknowns / (ms * 1e-3)}), flush=True)
+
+
 def source_sha(paths):
     import hashlib
 
@@ -137,6 +172,9 @@ def main():
                     help="skip the FP64 vs FP32-refinement record of the 2049^2 wireframe workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default=None,
+                    help="only time K solves of another workload (for profiling runs; no benchmark line)")
+    ap.add_argument("--precision", choices=["fp64", "fp32_ir"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); use --gpus 1",
@@ -167,6 +205,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload:
+        profile_workload(pkg, inputs, torch, dev, args)
+        return
     t0 = time.perf_counter()
     s = pkg.Solver([N_CELLS, N_CELLS], stretch=STRETCH, smoother="tweed", nu1=2, nu2=2, gamma=1,
                    precision="fp64", max_cycles=100, device=dev)

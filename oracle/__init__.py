@@ -12,7 +12,8 @@ What is here, with the passage of arXiv 2110.08389 each part follows:
 * ``coefs``             -- Section 2, W/E (S/N, B/T) coefficients of problem (DP).
 * ``Hierarchy``         -- Section 4 grid sequence, the smoothers of Section 3
                            (tweed, wireframe, checkerboard, zebra, alternating
-                           schemes) and Section 7 (3D tweed), the V/W cycle,
+                           schemes) and Section 7 (3D tweed; 3D alternating-
+                           direction zebra as x, y, z sweeps), the V/W cycle,
                            full/half weighting and bilinear/trilinear transfer.
 * ``spectral_radius``   -- Section 5, eq. (Mh2h): rho of the two-grid operator.
 """

@@ -44,6 +44,7 @@
 #include <omp.h>
 
 #define ORC_MAXLEV 32
+#define ORC_SLOTS 3 /* sweeps per relaxation: 3 for 3D alternating-direction zebra */
 
 /* number of OpenMP threads of the parallel loops (1 = the plain serial order) */
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
@@ -113,16 +114,17 @@ typedef struct {
     long nn;           /* total nodes                            */
     double *x[3];      /* coordinates                            */
     double *lo[3], *hi[3];
-    /* block partition for up to two smoother motifs (index 0 and 1) */
-    int nblk[2];
-    int *bstart[2];    /* block b occupies pts[bstart[b] .. bstart[b+1]) */
-    int *bpts[2];      /* node indices, ordered per the block shape      */
-    int *bshape[2];    /* BLK_*                                          */
-    int *bcolour[2];   /* 0 = red, 1 = black                             */
-    int *bnleg[2];     /* spider: number of legs                         */
-    int *blegstart[2]; /* spider: offset into blegs                      */
-    int *blegs[2];     /* spider: leg lengths (points, excl. branch)     */
-    int kind[2];       /* motif kind for slot 0/1 (-1 = unused)          */
+    /* block partition for up to three smoother motifs (slots 0, 1, 2: the
+     * sweeps of one relaxation, in order) */
+    int nblk[ORC_SLOTS];
+    int *bstart[ORC_SLOTS];    /* block b occupies pts[bstart[b] .. bstart[b+1]) */
+    int *bpts[ORC_SLOTS];      /* node indices, ordered per the block shape      */
+    int *bshape[ORC_SLOTS];    /* BLK_*                                          */
+    int *bcolour[ORC_SLOTS];   /* 0 = red, 1 = black                             */
+    int *bnleg[ORC_SLOTS];     /* spider: number of legs                         */
+    int *blegstart[ORC_SLOTS]; /* spider: offset into blegs                      */
+    int *blegs[ORC_SLOTS];     /* spider: leg lengths (points, excl. branch)     */
+    int kind[ORC_SLOTS];       /* motif kind of each slot (-1 = unused)          */
     /* coarsest direct solve (banded LU, no pivoting) */
     double *band;      /* factorised band                                */
     int bw;            /* half bandwidth                                 */
@@ -826,14 +828,21 @@ static void band_solve(const orc_mg *M, const orc_level *L, double *u, const dou
 /* Construction                                                              */
 /* ------------------------------------------------------------------------ */
 
-static int motif_slots(int smoother, int *k0, int *k1)
+/* The motifs of one relaxation, in sweep order.  Alternating-direction zebra
+ * is a zebra sweep along each axis in turn, x then y (then z in 3D: Section 7
+ * compares 3D tweed with these three sweeps); alternating tweed/wireframe is
+ * a tweed sweep then a wireframe sweep. */
+static int motif_slots(int smoother, int dim, int *k)
 {
-    *k0 = -1; *k1 = -1;
+    for (int s = 0; s < ORC_SLOTS; ++s) k[s] = -1;
     switch (smoother) {
     case ORC_TWEED: case ORC_WIREFRAME: case ORC_CHECKER: case ORC_ZEBRA_X: case ORC_ZEBRA_Y: case ORC_ZEBRA_Z:
-        *k0 = smoother; return 0;
-    case ORC_ADZ: *k0 = ORC_ZEBRA_X; *k1 = ORC_ZEBRA_Y; return 0;
-    case ORC_ALT_TW: *k0 = ORC_TWEED; *k1 = ORC_WIREFRAME; return 0;
+        k[0] = smoother; return 0;
+    case ORC_ADZ:
+        k[0] = ORC_ZEBRA_X; k[1] = ORC_ZEBRA_Y;
+        if (dim == 3) k[2] = ORC_ZEBRA_Z;
+        return 0;
+    case ORC_ALT_TW: k[0] = ORC_TWEED; k[1] = ORC_WIREFRAME; return 0;
     default: return -1;
     }
 }
@@ -849,8 +858,8 @@ void *orc_create(int dim, const int *n, double *const *coords, int smoother, int
     M->dim = dim;
     M->smoother = smoother;
     M->transpose = transpose;
-    int k0, k1;
-    if (motif_slots(smoother, &k0, &k1)) { free(M); return NULL; }
+    int km[ORC_SLOTS];
+    if (motif_slots(smoother, dim, km)) { free(M); return NULL; }
     int cur[3] = { n[0], n[1], dim == 3 ? n[2] : 0 };
     int lv = 0;
     for (;;) {
@@ -868,7 +877,7 @@ void *orc_create(int dim, const int *n, double *const *coords, int smoother, int
             else for (int i = 0; i <= L->n[a]; ++i) L->x[a][i] = M->lev[lv - 1].x[a][2 * i];
             orc_coefs(L->n[a], L->x[a], L->lo[a], L->hi[a]);
         }
-        L->kind[0] = L->kind[1] = -1;
+        for (int s = 0; s < ORC_SLOTS; ++s) L->kind[s] = -1;
         ++lv;
         int can = 1;
         for (int a = 0; a < dim; ++a) if (cur[a] % 2 != 0 || cur[a] < 4) can = 0;
@@ -886,8 +895,8 @@ void *orc_create(int dim, const int *n, double *const *coords, int smoother, int
         int odd = 0;
         for (int a = 0; a < dim; ++a) if (L->n[a] % 2) odd = 1;
         if (odd && l == M->nlev - 1 && l > 0) continue;
-        if (build_blocks(M, L, 0, k0)) { free(M); return NULL; }
-        if (k1 >= 0 && build_blocks(M, L, 1, k1)) { free(M); return NULL; }
+        for (int s = 0; s < ORC_SLOTS; ++s)
+            if (km[s] >= 0 && build_blocks(M, L, s, km[s])) { free(M); return NULL; }
     }
     /* the coarsest level's banded LU is built on first use (band_solve) */
     return M;
@@ -900,7 +909,7 @@ void orc_destroy(void *h)
     for (int l = 0; l < M->nlev; ++l) {
         orc_level *L = &M->lev[l];
         for (int a = 0; a < 3; ++a) { free(L->x[a]); free(L->lo[a]); free(L->hi[a]); }
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < ORC_SLOTS; ++s) {
             free(L->bstart[s]); free(L->bpts[s]); free(L->bshape[s]); free(L->bcolour[s]);
             free(L->bnleg[s]); free(L->blegstart[s]); free(L->blegs[s]);
         }
@@ -967,17 +976,19 @@ static int sweep(const orc_mg *M, const orc_level *L, int slot, double *u, const
 }
 
 /* One relaxation of the chosen smoother: for the alternating schemes (ADZ and
- * alternating tweed/wireframe) one relaxation is the pair of sweeps, which is
- * how the paper counts nu for them.  The adjoint runs the pair in reverse. */
+ * alternating tweed/wireframe) one relaxation is the pair (in 3D ADZ, the
+ * triple) of sweeps, which is how the paper counts nu for them.  The adjoint
+ * runs the sweeps in reverse order. */
 static int relax(const orc_mg *M, const orc_level *L, double *u, const double *f, int dense, int order)
 {
-    if (L->kind[1] < 0) return sweep(M, L, 0, u, f, dense, order);
-    if (!M->transpose) {
-        int rc = sweep(M, L, 0, u, f, dense, order);
-        return rc ? rc : sweep(M, L, 1, u, f, dense, order);
+    int ns = 0;
+    while (ns < ORC_SLOTS && L->kind[ns] >= 0) ++ns;
+    for (int k = 0; k < ns; ++k) {
+        int s = M->transpose ? ns - 1 - k : k;
+        int rc = sweep(M, L, s, u, f, dense, order);
+        if (rc) return rc;
     }
-    int rc = sweep(M, L, 1, u, f, dense, order);
-    return rc ? rc : sweep(M, L, 0, u, f, dense, order);
+    return 0;
 }
 
 int orc_smooth(void *h, int lv, double *u, const double *f, int nu, int dense, int order)

@@ -441,7 +441,9 @@ def test_coarse_banded_solve_equals_numpy():
     (2, [32, 32], "tweed", "tanh_wall", 3.0, 1),
     (2, [16, 16], "wireframe", "sinh_centre", 3.0, 2), (2, [32, 32], "adz", "tanh_wall", 2.5, 1),
     (2, [32, 16], "tweed", "tanh_wall", 2.0, 1), (2, [16, 16], "alt_tw", "tanh_wall", 2.0, 1),
-    (3, [8, 8, 8], "tweed", "tanh_wall", 2.5, 1), (3, [16, 16, 16], "tweed", "tanh_wall", 2.5, 1)])
+    (3, [8, 8, 8], "tweed", "tanh_wall", 2.5, 1), (3, [16, 16, 16], "tweed", "tanh_wall", 2.5, 1),
+    (3, [8, 8, 8], "adz", "tanh_wall", 2.5, 1), (3, [16, 16, 16], "adz", "tanh_wall", 2.5, 1),
+    (3, [16, 8, 12], "adz", "sinh_centre", 2.0, 1)])
 def test_cycles_reach_banded_lu(dim, n, smoother, kind, c, gamma):
     xs = [O.coords(kind, c, k) for k in n]
     H = O.Hierarchy(xs, smoother)
@@ -599,3 +601,65 @@ def test_threads_bitwise_identical(n, kind, c, sm):
         O.set_threads(old)
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+
+# ----------------------------------------------------------------------------
+# 3D alternating-direction zebra (Section 7: the three-sweep comparison scheme)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,kind,c", [([8, 8, 8], "tanh_wall", 2.5), ([12, 8, 10], "sinh_centre", 3.0)])
+def test_adz_3d_is_three_zebra_sweeps(n, kind, c):
+    """One 3D ADZ relaxation is a zebra sweep along x, then along y, then along
+    z (each red lines then black lines); its adjoint runs z, y, x on the
+    transposed operator.  Checked by composing the single-direction
+    smoothers, which are pinned on their own (partition, block solves)."""
+    xs = [O.coords(kind, c, k) for k in n]
+    rng = np.random.default_rng(21)
+    shape = O.Hierarchy(xs, "adz", maxlev=1).shape(0)
+    u = rng.standard_normal(shape)
+    f = rng.standard_normal(shape)
+    for tr, order in ((False, ("zebra_x", "zebra_y", "zebra_z")), (True, ("zebra_z", "zebra_y", "zebra_x"))):
+        want = u.copy()
+        for sm in order:
+            want = O.Hierarchy(xs, sm, transpose=tr, maxlev=1).smooth(want, f, 1)
+        got = O.Hierarchy(xs, "adz", transpose=tr, maxlev=1).smooth(u, f, 1)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("sm,ax", [("zebra_x", 0), ("zebra_y", 1), ("zebra_z", 2)])
+def test_zebra_3d_lines_cover_each_point_once(sm, ax):
+    """Every interior point lies on exactly one line of each direction, each
+    line runs along its axis across the whole interior, and neighbouring lines
+    have opposite colours."""
+    n = [6, 8, 4]
+    xs = [O.coords("uniform", 0, k) for k in n]
+    H = O.Hierarchy(xs, sm, maxlev=1)
+    owner, colour = _point_block(H)
+    m = interior_index(owner.shape)
+    assert np.all(owner[m] >= 0)
+    for blk in H.blocks():
+        assert blk["size"] == n[ax] - 1
+    for a in range(3):
+        if a == ax:
+            continue
+        sl_a = [slice(1, -1)] * 3
+        sl_b = [slice(1, -1)] * 3
+        arr_ax = 2 - a
+        sl_a[arr_ax] = slice(1, -2)
+        sl_b[arr_ax] = slice(2, -1)
+        assert np.all(colour[tuple(sl_a)] != colour[tuple(sl_b)])
+
+
+def test_adz_3d_converges_where_3d_tweed_slows():
+    """Section 7 names 3D alternating-direction zebra as the 3D comparison for
+    3D tweed, which on grids stretched in all three directions degrades as
+    the grid grows.  On the wall-clustered 33^3 grid (tanh, c = 2.5) the ADZ
+    V(2,2) cycle (three zebra sweeps per relaxation) reduces the defect by
+    more than a factor 10 per cycle and about twice as fast as 3D tweed there
+    (this build measures 0.065 and 0.134 per cycle)."""
+    x = O.coords("tanh_wall", 2.5, 32)
+    f = np.random.default_rng(3).uniform(-1, 1, (33, 33, 33))
+    ra = _factor(O.Hierarchy([x, x, x], "adz"), f)
+    rt = _factor(O.Hierarchy([x, x, x], "tweed"), f)
+    assert ra < 0.1 and ra < rt / 1.5, (ra, rt)
