@@ -64,7 +64,8 @@ def lib():
         L.orc_get_threads.argtypes = []
         L.orc_coords.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, dp]
         L.orc_coefs.argtypes = [C.c_int, dp, dp, dp]
-        L.orc_create.argtypes = [C.c_int, ip, C.POINTER(dp), C.c_int, C.c_int, C.c_int]
+        L.orc_coefs_sigma.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.orc_create.argtypes = [C.c_int, ip, C.POINTER(dp), C.POINTER(dp), C.c_int, C.c_int, C.c_int]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_nlevels.argtypes = [C.c_void_p]
@@ -121,13 +122,20 @@ def coords(kind, param: float, n: int, L: float = 1.0) -> np.ndarray:
     return x
 
 
-def coefs(x: np.ndarray):
-    """Section 2 coefficients (lo = W/S/B, hi = E/N/T) on node coordinates x."""
+def coefs(x: np.ndarray, sigma=None):
+    """Section 2 coefficients (lo = W/S/B, hi = E/N/T) on node coordinates x;
+    with sigma (one value per cell) the flux form of problem (CP) with that
+    axis-wise conductivity."""
     n = len(x) - 1
     lo = np.zeros(n + 1)
     hi = np.zeros(n + 1)
     x = np.ascontiguousarray(x, dtype=np.float64)
-    lib().orc_coefs(n, _dp(x), _dp(lo), _dp(hi))
+    if sigma is None:
+        lib().orc_coefs(n, _dp(x), _dp(lo), _dp(hi))
+    else:
+        sg = np.ascontiguousarray(sigma, dtype=np.float64)
+        assert sg.shape == (n,)
+        lib().orc_coefs_sigma(n, _dp(x), _dp(sg), _dp(lo), _dp(hi))
     return lo, hi
 
 
@@ -140,16 +148,25 @@ class Hierarchy:
     entries of ``u`` hold the Dirichlet data.
     """
 
-    def __init__(self, coord_list, smoother="tweed", transpose=False, maxlev=0):
+    def __init__(self, coord_list, smoother="tweed", transpose=False, maxlev=0, sigma=None):
         self.dim = len(coord_list)
         self.n = [len(c) - 1 for c in coord_list]
         self._coords = [np.ascontiguousarray(c, dtype=np.float64) for c in coord_list]
         ptrs = (C.POINTER(C.c_double) * 3)(*[_dp(c) for c in self._coords],
                                            *([None] * (3 - self.dim)))
+        # optional axis-wise conductivity: sigma[a] holds one value per cell
+        # of axis a (None: 1 on that axis)
+        self._sig = [None if sigma is None or sigma[a] is None
+                     else np.ascontiguousarray(sigma[a], dtype=np.float64) for a in range(self.dim)]
+        for a, sg in enumerate(self._sig):
+            if sg is not None and sg.shape != (self.n[a],):
+                raise ValueError("sigma: one value per cell on each axis")
+        sptrs = (C.POINTER(C.c_double) * 3)(*[_dp(sg) if sg is not None else None for sg in self._sig],
+                                            *([None] * (3 - self.dim)))
         n3 = np.array(self.n + [0] * (3 - self.dim), dtype=np.int32)
         sm = SMOOTHERS[smoother] if isinstance(smoother, str) else smoother
         self.smoother = sm
-        self.h = lib().orc_create(self.dim, _ip(n3), ptrs, sm, int(transpose), int(maxlev))
+        self.h = lib().orc_create(self.dim, _ip(n3), ptrs, sptrs, sm, int(transpose), int(maxlev))
         if not self.h:
             raise ValueError("oracle: cannot build hierarchy")
         self.nlev = lib().orc_nlevels(self.h)

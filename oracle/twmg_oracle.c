@@ -104,6 +104,39 @@ void orc_coefs(int n, const double *x, double *lo, double *hi)
     }
 }
 
+/* The axis-wise heterogeneous, anisotropic form of problem (CP) (Section 2)
+ * with a diagonal conductivity whose a-th entry depends on x_a only,
+ * sigma_aa = s_a(x_a): the flux form of the same three-point difference,
+ *     W_i = s_{i-1/2}/(dx dxm),  E_i = s_{i+1/2}/(dx dxp),
+ * with sig[k] = s_{k+1/2}, the value on cell k = [x_k, x_{k+1}] (n values).
+ * sig == NULL is s = 1 (orc_coefs).                        (READING: extension) */
+void orc_coefs_sigma(int n, const double *x, const double *sig, double *lo, double *hi)
+{
+    orc_coefs(n, x, lo, hi);
+    if (!sig) return;
+    for (int i = 1; i < n; ++i) {
+        double dxm = x[i] - x[i - 1];
+        double dxp = x[i + 1] - x[i];
+        double dx = (x[i + 1] - x[i - 1]) / 2.0;
+        lo[i] = sig[i - 1] / (dx * dxm);
+        hi[i] = sig[i] / (dx * dxp);
+    }
+}
+
+/* Coarse-cell conductivity (READING: the paper re-discretises on the coarse
+ * coordinates and leaves heterogeneous media to standard methods): coarse cell
+ * I covers fine cells 2I and 2I+1 in series, so its value is their
+ * length-weighted harmonic mean, (h0 + h1)/(h0/s0 + h1/s1) -- the conductance
+ * of the two cells in series, which keeps the coarse flux of a piecewise
+ * linear-in-1/s profile exact. */
+static void coarse_sigma(int nc, const double *xf, const double *sf, double *sc)
+{
+    for (int I = 0; I < nc; ++I) {
+        double h0 = xf[2 * I + 1] - xf[2 * I], h1 = xf[2 * I + 2] - xf[2 * I + 1];
+        sc[I] = (h0 + h1) / (h0 / sf[2 * I] + h1 / sf[2 * I + 1]);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid hierarchy                                                            */
 /* ------------------------------------------------------------------------ */
@@ -113,6 +146,7 @@ typedef struct {
     int np[3];         /* nodes per axis = n+1 (np[2] = 1 in 2D) */
     long nn;           /* total nodes                            */
     double *x[3];      /* coordinates                            */
+    double *sig[3];    /* per-cell conductivity along each axis (NULL: 1) */
     double *lo[3], *hi[3];
     /* block partition for up to three smoother motifs (slots 0, 1, 2: the
      * sweeps of one relaxation, in order) */
@@ -851,7 +885,8 @@ static int motif_slots(int smoother, int dim, int *k)
  * node coordinates (n[a]+1 values each).  maxlev <= 0 means "as deep as the
  * coarsening rule allows"; otherwise at most maxlev levels (2 gives the
  * two-grid pair used for the spectral radii of Section 5). */
-void *orc_create(int dim, const int *n, double *const *coords, int smoother, int transpose, int maxlev)
+void *orc_create(int dim, const int *n, double *const *coords, double *const *sigma, int smoother, int transpose,
+                 int maxlev)
 {
     if (dim != 2 && dim != 3) return NULL;
     orc_mg *M = (orc_mg *)calloc(1, sizeof(orc_mg));
@@ -875,7 +910,13 @@ void *orc_create(int dim, const int *n, double *const *coords, int smoother, int
             L->hi[a] = (double *)malloc(sizeof(double) * (L->n[a] + 1));
             if (lv == 0) memcpy(L->x[a], coords[a], sizeof(double) * (L->n[a] + 1));
             else for (int i = 0; i <= L->n[a]; ++i) L->x[a][i] = M->lev[lv - 1].x[a][2 * i];
-            orc_coefs(L->n[a], L->x[a], L->lo[a], L->hi[a]);
+            L->sig[a] = NULL;
+            if (sigma && sigma[a]) {
+                L->sig[a] = (double *)malloc(sizeof(double) * L->n[a]);
+                if (lv == 0) memcpy(L->sig[a], sigma[a], sizeof(double) * L->n[a]);
+                else coarse_sigma(L->n[a], M->lev[lv - 1].x[a], M->lev[lv - 1].sig[a], L->sig[a]);
+            }
+            orc_coefs_sigma(L->n[a], L->x[a], L->sig[a], L->lo[a], L->hi[a]);
         }
         for (int s = 0; s < ORC_SLOTS; ++s) L->kind[s] = -1;
         ++lv;
@@ -908,7 +949,7 @@ void orc_destroy(void *h)
     if (!M) return;
     for (int l = 0; l < M->nlev; ++l) {
         orc_level *L = &M->lev[l];
-        for (int a = 0; a < 3; ++a) { free(L->x[a]); free(L->lo[a]); free(L->hi[a]); }
+        for (int a = 0; a < 3; ++a) { free(L->x[a]); free(L->lo[a]); free(L->hi[a]); free(L->sig[a]); }
         for (int s = 0; s < ORC_SLOTS; ++s) {
             free(L->bstart[s]); free(L->bpts[s]); free(L->bshape[s]); free(L->bcolour[s]);
             free(L->bnleg[s]); free(L->blegstart[s]); free(L->blegs[s]);

@@ -663,3 +663,90 @@ def test_adz_3d_converges_where_3d_tweed_slows():
     ra = _factor(O.Hierarchy([x, x, x], "adz"), f)
     rt = _factor(O.Hierarchy([x, x, x], "tweed"), f)
     assert ra < 0.1 and ra < rt / 1.5, (ra, rt)
+
+
+# ----------------------------------------------------------------------------
+# Axis-wise heterogeneous, anisotropic conductivity (problem (CP), Section 2,
+# with sigma_aa = s_a(x_a) and no cross terms)
+# ----------------------------------------------------------------------------
+
+def _sigma_profile(n, seed):
+    """A strongly varying positive conductivity, one value per cell."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(-3.0, 3.0, n))
+
+
+def test_sigma_constant_scales_the_operator():
+    """A constant conductivity c on an axis multiplies that axis' coefficients
+    by c (problem (CP) with sigma = c delta reduces to c times problem (DP))."""
+    x = O.coords("tanh_wall", 2.0, 24)
+    lo, hi = O.coefs(x)
+    los, his = O.coefs(x, np.full(24, 7.5))
+    np.testing.assert_allclose(los, 7.5 * lo, rtol=1e-15)
+    np.testing.assert_allclose(his, 7.5 * hi, rtol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sigma_flux_form_exact_on_constant_flux(dim):
+    """With u_a = sum over the cells left of a node of (cell length)/s, the
+    discrete flux s (u_{i+1} - u_i)/(x_{i+1} - x_i) is 1 on every cell, so the
+    flux-form operator annihilates u = U(x) + V(y) [+ Z(z)] and U(x) V(y)
+    [Z(z)] exactly, on every level of the hierarchy: the coarse operator uses
+    the series (harmonic) average of the two fine cells, under which the
+    coarse-node values of U are again the discrete integral of 1/s.  An
+    arithmetic coarse average fails this on the coarse levels."""
+    n = [32, 16, 16][:dim]
+    kinds = [("tanh_wall", 2.5), ("sinh_centre", 3.0), ("tanh_centre", 1.5)][:dim]
+    xs = [O.coords(k, c, m) for (k, c), m in zip(kinds, n)]
+    sig = [_sigma_profile(m, 30 + a) for a, m in enumerate(n)]
+    H = O.Hierarchy(xs, "tweed", sigma=sig)
+    for lv in range(H.nlev - 1):
+        xl = [H.level_coefs(lv, a)[0] for a in range(dim)]
+        step = 2 ** lv
+        prims = []
+        for a in range(dim):
+            # the discrete integral of 1/s on the finest cells, sampled at the
+            # level's nodes (every step-th fine node)
+            full = np.concatenate([[0.0], np.cumsum(np.diff(xs[a]) / sig[a])])
+            prims.append(full[::step])
+            assert np.allclose(xl[a], xs[a][::step], rtol=0, atol=0)
+        grids = np.meshgrid(*reversed(prims), indexing="ij")
+        for u in (sum(grids), np.prod(grids, axis=0)):
+            got = H.apply(u, lv)
+            m = H.interior_mask(lv)
+            scale = max(np.max(np.abs(H.level_coefs(lv, a)[1])) for a in range(dim)) * np.max(np.abs(u))
+            assert np.max(np.abs(got[m])) < 1e-12 * scale, lv
+
+
+def test_sigma_DA_symmetric():
+    """D A stays symmetric with D = diag(dx_i dy_j): the flux between nodes i-1
+    and i carries the same s_{i-1/2} in both rows."""
+    x = O.coords("tanh_wall", 2.5, 10)
+    y = O.coords("sinh_centre", 3.0, 8)
+    H = O.Hierarchy([x, y], "tweed", sigma=[_sigma_profile(10, 1), _sigma_profile(8, 2)])
+    A, mask = dense_operator(H)
+    dx = (x[2:] - x[:-2]) / 2
+    dy = (y[2:] - y[:-2]) / 2
+    DA = np.outer(dy, dx).ravel()[:, None] * A
+    assert np.max(np.abs(DA - DA.T)) < 1e-12 * np.max(np.abs(DA))
+
+
+@pytest.mark.parametrize("dim,n,sm,kind,c,gamma", [(2, [32, 32], "tweed", "tanh_wall", 2.5, 1),
+                                                   (2, [32, 32], "alt_tw", "tanh_wall", 2.0, 1),
+                                                   (2, [32, 16], "zebra_x", "uniform", 0.0, 1),
+                                                   (3, [16, 16, 16], "adz", "tanh_wall", 2.0, 1)])
+def test_sigma_cycles_reach_banded_lu(dim, n, sm, kind, c, gamma):
+    """Strongly heterogeneous (a factor e^6 between cells) and anisotropic
+    conductivity: the cycles converge to the banded-LU solution of the same
+    discrete system."""
+    xs = [O.coords(kind, c, k) for k in n]
+    sig = [_sigma_profile(k, 40 + a) for a, k in enumerate(n)]
+    if sm == "zebra_x":
+        sig[0] = sig[0] * 100.0   # strong x-coupling: x-lines are the right smoother
+    H = O.Hierarchy(xs, sm, sigma=sig)
+    rng = np.random.default_rng(5)
+    f = rng.uniform(-1, 1, H.shape())
+    g = np.zeros(H.shape())
+    u, k, hist, st = H.solve(g, f, gamma=gamma, tol=1e-12, max_cycles=200)
+    assert st == 0, (k, hist[-3:])
+    assert rel_inf(u, H.direct(g, f)) < 1e-7
