@@ -72,10 +72,18 @@ typedef struct {
     int batch;        /* independent problems sharing the grid (>= 1)                 */
 } mg_grid;
 
+/* Grid and medium.  sigma[a] (optional, host, n[a] positive finite values)
+ * is the conductivity along axis a, one value per cell [x_k, x_{k+1}]: the
+ * axis-wise heterogeneous, anisotropic form of problem (CP) of Section 2
+ * with sigma_ij = diag(s_x(x), s_y(y)[, s_z(z)]) (no cross terms), discretised
+ * in flux form, W_i = s_{i-1/2}/(dx_i dx_{i-1/2}), E_i = s_{i+1/2}/(dx_i
+ * dx_{i+1/2}); a coarse cell takes the series conductance of its two fine
+ * cells, (h0 + h1)/(h0/s0 + h1/s1).  NULL means s = 1 (problem (DP)). */
 typedef struct {
     int kind[3];            /* mg_stretch_kind per axis                              */
     double param[3];        /* c (tanh) or b (sinh) per axis                         */
     const double *coords[3];/* MG_EXPLICIT: host arrays of n[a]+1 coordinates        */
+    const double *sigma[3]; /* optional: host arrays of n[a] cell conductivities     */
 } mg_stretching;
 
 typedef struct {
@@ -215,8 +223,8 @@ int mg_smooth_f32(mg_handle *h, int lv, float *u, const float *f, int nu, int ad
  * mg_to_layout / mg_from_layout: row-major <-> device layout (all problems of
  *   the batch); src and dst must not overlap.
  * mg_half_sweep: one half-sweep -- every block of one colour (0 red, 1 black)
- *   of motif slot `slot` (0, or 1 for the second motif of an alternating
- *   smoother) solved exactly with the other colour frozen -- on arrays in the
+ *   of motif slot `slot` (0; 1 and 2 for the second and third sweeps of an
+ *   alternating smoother) solved exactly with the other colour frozen -- on arrays in the
  *   device layout.  MG_EINVAL for the checkerboard smoother or a slot the
  *   smoother does not have. */
 int mg_level_array_len(const mg_handle *h, int lv, long long *len);

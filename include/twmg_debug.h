@@ -12,8 +12,8 @@
 extern "C" {
 #endif
 
-/* Statistics of the block table of level lv, motif slot (0, or 1 for the
- * second motif of an alternating smoother) and colour (0 red, 1 black):
+/* Statistics of the block table of level lv, motif slot (0; 1 and 2 for the
+ * later sweeps of an alternating smoother) and colour (0 red, 1 black):
  * info[0] workgroups, [1] chunks, [2] blocks, [3] max chunks in a workgroup,
  * [4] max blocks in a workgroup, [5] points covered.  Host memory. */
 int mg_debug_table_info(const mg_handle *h, int lv, int slot, int colour, int *info);

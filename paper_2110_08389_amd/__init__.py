@@ -27,7 +27,8 @@ class mg_grid(C.Structure):
 
 
 class mg_stretching(C.Structure):
-    _fields_ = [("kind", C.c_int * 3), ("param", C.c_double * 3), ("coords", C.POINTER(C.c_double) * 3)]
+    _fields_ = [("kind", C.c_int * 3), ("param", C.c_double * 3), ("coords", C.POINTER(C.c_double) * 3),
+                ("sigma", C.POINTER(C.c_double) * 3)]
 
 
 class mg_options(C.Structure):
@@ -121,7 +122,7 @@ class Solver:
     """
 
     def __init__(self, n, L=None, stretch=("uniform", 0.0), smoother="tweed", nu1=2, nu2=2, gamma=1,
-                 precision="fp64", max_cycles=200, batch=1, coords=None, device=None, stream=None):
+                 precision="fp64", max_cycles=200, batch=1, coords=None, sigma=None, device=None, stream=None):
         import torch
 
         self.torch = torch
@@ -147,6 +148,12 @@ class Solver:
                 buf = (C.c_double * (n[a] + 1))(*[float(v) for v in coords[a]])
                 self._coord_bufs.append(buf)
                 st.coords[a] = C.cast(buf, C.POINTER(C.c_double))
+            if sigma is not None and sigma[a] is not None:
+                if len(sigma[a]) != n[a]:
+                    raise ValueError("sigma: one conductivity per cell on each axis")
+                buf = (C.c_double * n[a])(*[float(v) for v in sigma[a]])
+                self._coord_bufs.append(buf)
+                st.sigma[a] = C.cast(buf, C.POINTER(C.c_double))
         self.opts = mg_options()
         self.opts.smoother = SMOOTHER[smoother]
         self.opts.nu1, self.opts.nu2, self.opts.gamma = int(nu1), int(nu2), int(gamma)

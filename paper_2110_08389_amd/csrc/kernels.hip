@@ -1487,12 +1487,26 @@ __global__ void __launch_bounds__(256) k_resnorm_tile(Dims d, Coef<T> cf, const 
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
 }
 
-// per-problem maximum: workgroup b reduces problem b's n partial maxima into out[b]
-__global__ void __launch_bounds__(256) k_max_final(const double *__restrict__ partial, int n, double *__restrict__ out)
+// per-problem maximum: workgroup b reduces problem b's n partial maxima into
+// out[b].  Each lane issues its 8 loads of a step before combining them, so a
+// step costs one memory round trip (the partials hold no NaN: a NaN defect is
+// recorded as +inf).
+constexpr int MAXF_NT = 1024, MAXF_U = 8;
+__global__ void __launch_bounds__(MAXF_NT) k_max_final(const double *__restrict__ partial, int n,
+                                                       double *__restrict__ out)
 {
     const double *pb = partial + (long long)blockIdx.x * n;
     double m = 0.0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, pb[k]);
+    for (int k0 = threadIdx.x; k0 < n; k0 += MAXF_NT * MAXF_U) {
+        double v[MAXF_U];
+#pragma unroll
+        for (int q = 0; q < MAXF_U; ++q) {
+            const int k = k0 + q * MAXF_NT;
+            v[q] = k < n ? pb[k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < MAXF_U; ++q) m = fmax(m, v[q]);
+    }
     m = block_max(m);
     if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
@@ -1512,7 +1526,7 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
     } else {
         hipLaunchKernelGGL((k_resnorm<T, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     }
-    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(256), 0, s, partial, gx, out);
+    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
     return hipGetLastError();
 }
 
@@ -1531,7 +1545,7 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
     } else {
         hipLaunchKernelGGL((k_resnorm<double, 3, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
-    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(256), 0, s, partial, gx, out);
+    hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
     return hipGetLastError();
 }
 
@@ -1590,7 +1604,7 @@ hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const do
                            partial);
     }
     // one workgroup over all problems' partial maxima: the batch's maximum
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, gx * batch, out);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(MAXF_NT), 0, s, partial, gx * batch, out);
     return hipGetLastError();
 }
 

@@ -62,16 +62,35 @@ int make_coords(int kind, double c, int n, double L, const double *given, std::v
     return MG_OK;
 }
 
-// Section 2: W_i = 1/(dx_i dx_{i-1/2}), E_i = 1/(dx_i dx_{i+1/2}), dx_i = (x_{i+1}-x_{i-1})/2
-void make_coefs(const std::vector<double> &x, std::vector<double> &lo, std::vector<double> &hi)
+// Section 2: W_i = 1/(dx_i dx_{i-1/2}), E_i = 1/(dx_i dx_{i+1/2}), dx_i = (x_{i+1}-x_{i-1})/2.
+// With a conductivity along the axis (problem (CP) with sigma_aa = s(x_a);
+// sig[k] is its value on cell k = [x_k, x_{k+1}], empty for s = 1), the
+// flux form: the numerators become s_{i-1/2} and s_{i+1/2}.
+void make_coefs(const std::vector<double> &x, const std::vector<double> &sig, std::vector<double> &lo,
+                std::vector<double> &hi)
 {
     const int n = (int)x.size() - 1;
     lo.assign(n + 1, 0.0);
     hi.assign(n + 1, 0.0);
     for (int i = 1; i < n; ++i) {
         const double hm = x[i] - x[i - 1], hp = x[i + 1] - x[i], h = 0.5 * (x[i + 1] - x[i - 1]);
-        lo[i] = 1.0 / (h * hm);
-        hi[i] = 1.0 / (h * hp);
+        lo[i] = (sig.empty() ? 1.0 : sig[i - 1]) / (h * hm);
+        hi[i] = (sig.empty() ? 1.0 : sig[i]) / (h * hp);
+    }
+}
+
+// conductivity of the coarse cells: coarse cell I is fine cells 2I and 2I+1
+// in series, so its conductance is theirs combined in series, length over
+// the sum of length/conductivity
+void coarsen_sigma(const std::vector<double> &xf, const std::vector<double> &sf, std::vector<double> &sc)
+{
+    sc.clear();
+    if (sf.empty()) return;
+    const int nc = (int)(xf.size() - 1) / 2;
+    sc.resize(nc);
+    for (int c = 0; c < nc; ++c) {
+        const double a = xf[2 * c + 1] - xf[2 * c], b = xf[2 * c + 2] - xf[2 * c + 1];
+        sc[c] = (a + b) / (a / sf[2 * c] + b / sf[2 * c + 1]);
     }
 }
 
@@ -767,11 +786,12 @@ struct Level {
     Dims d;
     Grid3 g;
     std::vector<double> x[3], lo[3], hi[3];
+    std::vector<double> sig[3]; // conductivity per cell along each axis (empty: 1)
     Coef<double> c64[2];  // [forward, transposed]
     Coef<float> c32[2];
-    SweepTable tab[2][2]; // [motif slot][colour]
-    HostTable htab[2][2]; // host copies (validation and the host emulation hook)
-    std::vector<NodeFac<double>> hfac[2][2][2]; // [slot][colour][forward/transposed]
+    SweepTable tab[MAXSLOT][2]; // [motif slot][colour]
+    HostTable htab[MAXSLOT][2]; // host copies (validation and the host emulation hook)
+    std::vector<NodeFac<double>> hfac[MAXSLOT][2][2]; // [slot][colour][forward/transposed]
     long long cs = 0;                 // entries per coefficient array
     std::vector<double> hblk[2];      // host coefficient blocks [forward, transposed] (layout of Coef)
     Coef<double> hc64[2];
@@ -788,7 +808,7 @@ struct mg_handle {
     SideStream side;          // overlaps big-block launches with the rest of a half-sweep
     int nlev = 0;
     Level lev[MAXLEV];
-    int slot_motif[2] = {-1, -1};
+    int slot_motif[MAXSLOT] = {-1, -1, -1};
     bool checker = false;
     int nunk_coarse = 0;
     double *cinv64[2] = {nullptr, nullptr};
@@ -908,36 +928,46 @@ bool invert(std::vector<double> &A, int n, std::vector<double> &inv)
     return true;
 }
 
-int motif_slots(int smoother, int dim, int *m0, int *m1, bool *checker)
+int motif_slots(int smoother, int dim, int *m, bool *checker)
 {
-    *m0 = *m1 = -1;
+    for (int s = 0; s < MAXSLOT; ++s) m[s] = -1;
     *checker = false;
     switch (smoother) {
-    case MG_TWEED: *m0 = M_TWEED; break;
+    case MG_TWEED: m[0] = M_TWEED; break;
     case MG_WIREFRAME:
         if (dim != 2) return MG_EUNSUPPORTED;
-        *m0 = M_WIREFRAME;
+        m[0] = M_WIREFRAME;
         break;
     case MG_CHECKERBOARD: *checker = true; break;
-    case MG_ZEBRA_X: *m0 = M_ZX; break;
-    case MG_ZEBRA_Y: *m0 = M_ZY; break;
+    case MG_ZEBRA_X: m[0] = M_ZX; break;
+    case MG_ZEBRA_Y: m[0] = M_ZY; break;
     case MG_ZEBRA_Z:
         if (dim != 3) return MG_EINVAL;
-        *m0 = M_ZZ;
+        m[0] = M_ZZ;
         break;
     case MG_ADZ:
-        *m0 = M_ZX;
-        *m1 = M_ZY;
-        if (dim == 3) return MG_EUNSUPPORTED; // three-direction variant not provided
+        // a zebra sweep along each axis in turn (Section 7's 3D comparison
+        // scheme takes the third, along z)
+        m[0] = M_ZX;
+        m[1] = M_ZY;
+        if (dim == 3) m[2] = M_ZZ;
         break;
     case MG_ALT_TW:
         if (dim != 2) return MG_EUNSUPPORTED;
-        *m0 = M_TWEED;
-        *m1 = M_WIREFRAME;
+        m[0] = M_TWEED;
+        m[1] = M_WIREFRAME;
         break;
     default: return MG_EINVAL;
     }
     return MG_OK;
+}
+
+// number of sweeps (motif slots) in one relaxation
+int nslots(const mg_handle *h)
+{
+    int ns = 0;
+    while (ns < MAXSLOT && h->slot_motif[ns] >= 0) ++ns;
+    return ns;
 }
 
 // ---------------------------------------------------------------------------
@@ -964,7 +994,7 @@ void tail_ops_rec(const mg_handle *h, int lt, int lv, int adj, int map_lv, std::
             for (int k = 0; k < 2; ++k) ops.push_back(TailOp{TO_CHECKER, rel, 0, (uint8_t)(adj ? 1 - k : k)});
             return;
         }
-        const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+        const int ns = nslots(h);
         for (int k = 0; k < ns; ++k) {
             const int sl = adj ? ns - 1 - k : k;
             for (int q = 0; q < 2; ++q) ops.push_back(TailOp{TO_SWEEP, rel, (uint8_t)sl, (uint8_t)(adj ? 1 - q : q)});
@@ -1015,12 +1045,12 @@ size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char
         }
         if (lt + r == h->nlev - 1) continue;
         t.short_chunks = 1;
-        for (int sl = 0; sl < 2; ++sl)
+        for (int sl = 0; sl < MAXSLOT; ++sl)
             for (int c = 0; c < 2; ++c)
                 if (h->slot_motif[sl] >= 0)
                     for (const Chunk &ch : L.htab[sl][c].chunks)
                         if (ch.len > TAIL_SHORT_CH) t.short_chunks = 0;
-        for (int sl = 0; sl < 2; ++sl)
+        for (int sl = 0; sl < MAXSLOT; ++sl)
             for (int c = 0; c < 2; ++c) {
                 if (h->slot_motif[sl] < 0) continue;
                 const HostTable &ht = L.htab[sl][c];
@@ -1144,7 +1174,7 @@ int build_tail(mg_handle *h)
     int lt = -1;
     for (int l = nl - 2; l >= 0; --l) {
         bool fits = h->lev[l].d.layout == LAYOUT_ROW;
-        for (int sl = 0; sl < 2; ++sl)
+        for (int sl = 0; sl < MAXSLOT; ++sl)
             for (int c = 0; c < 2; ++c)
                 fits = fits && h->lev[l].tab[sl][c].nwg_big == 0 && h->lev[l].tab[sl][c].nts == NT / 2;
         std::vector<unsigned char> img;
@@ -1216,7 +1246,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     if (opt->precision != MG_FP64 && opt->precision != MG_FP32_IR) return MG_EINVAL;
     h->grid = *grid;
     h->opt = *opt;
-    int rc = motif_slots(opt->smoother, grid->dim, &h->slot_motif[0], &h->slot_motif[1], &h->checker);
+    int rc = motif_slots(opt->smoother, grid->dim, h->slot_motif, &h->checker);
     if (rc) return rc;
     const int dim = grid->dim;
     // finest coordinates
@@ -1224,6 +1254,9 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     for (int a = 0; a < dim; ++a) {
         rc = make_coords(st->kind[a], st->param[a], grid->n[a], grid->L[a], st->coords[a], x0[a]);
         if (rc) return rc;
+        if (st->sigma[a])
+            for (int k = 0; k < grid->n[a]; ++k)
+                if (!(st->sigma[a][k] > 0) || std::isinf(st->sigma[a][k])) return MG_EINVAL;
     }
     // hierarchy (Section 4): coarse nodes are every other fine node; stop when an
     // axis has an odd number of cells or only two
@@ -1264,12 +1297,15 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
         for (int a = 0; a < dim; ++a) {
-            if (nl == 0) L.x[a] = x0[a];
-            else {
+            if (nl == 0) {
+                L.x[a] = x0[a];
+                if (st->sigma[a]) L.sig[a].assign(st->sigma[a], st->sigma[a] + cur[a]);
+            } else {
                 L.x[a].resize(cur[a] + 1);
                 for (int i = 0; i <= cur[a]; ++i) L.x[a][i] = h->lev[nl - 1].x[a][2 * i];
+                coarsen_sigma(h->lev[nl - 1].x[a], h->lev[nl - 1].sig[a], L.sig[a]);
             }
-            make_coefs(L.x[a], L.lo[a], L.hi[a]);
+            make_coefs(L.x[a], L.sig[a], L.lo[a], L.hi[a]);
         }
         ++nl;
         bool can = true;
@@ -1324,7 +1360,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     // block tables for every level that is smoothed
     for (int l = 0; l + 1 < nl; ++l) {
         Level &L = h->lev[l];
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < MAXSLOT; ++s) {
             if (h->slot_motif[s] < 0) continue;
             // levels small enough for the coarse-level kernel: chunks of
             // CH - 1 points (its lanes read their chunks' points from LDS
@@ -1458,7 +1494,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     if (!h->pool.host_only) {
         bool big = false;
         for (int l = 0; l + 1 < h->nlev; ++l)
-            for (int sl = 0; sl < 2; ++sl)
+            for (int sl = 0; sl < MAXSLOT; ++sl)
                 for (int c = 0; c < 2; ++c) big = big || h->lev[l].tab[sl][c].nwg_big > 0;
         if (big) {
             HIPCHK(hipStreamCreateWithFlags(&h->side.aux, hipStreamNonBlocking));
@@ -1497,7 +1533,7 @@ template <typename T> int relax(mg_handle *h, int lv, T *u, const T *f, int adj)
         for (int k = 0; k < 2; ++k) HIPCHK(launch_checker<T>(L.d, c, u, f, adj ? 1 - k : k, B, h->stream));
         return MG_OK;
     }
-    const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+    const int ns = nslots(h);
     for (int k = 0; k < ns; ++k) {
         const int s = adj ? ns - 1 - k : k;
         for (int q = 0; q < 2; ++q) {
@@ -1697,11 +1733,13 @@ int mg_set_options(mg_handle *h, const mg_options *opt)
     if (!h || !opt) return MG_EINVAL;
     if (opt->nu1 < 0 || opt->nu2 < 0 || opt->gamma < 1 || opt->gamma > 2 || opt->max_cycles < 1) return MG_EINVAL;
     if (opt->precision != MG_FP64 && opt->precision != MG_FP32_IR) return MG_EINVAL;
-    int m0, m1;
+    int m[MAXSLOT];
     bool ck;
-    const int rc = motif_slots(opt->smoother, h->grid.dim, &m0, &m1, &ck);
+    const int rc = motif_slots(opt->smoother, h->grid.dim, m, &ck);
     if (rc) return rc;
-    if (!ck && (m0 != h->slot_motif[0] || m1 != h->slot_motif[1])) return MG_EINVAL;
+    if (!ck)
+        for (int s = 0; s < MAXSLOT; ++s)
+            if (m[s] != h->slot_motif[s]) return MG_EINVAL;
     h->opt = *opt;
     h->checker = ck;
     return build_tail(h);
@@ -1971,7 +2009,7 @@ int mg_from_layout(mg_handle *h, int lv, const double *src, double *dst)
 
 int mg_half_sweep(mg_handle *h, int lv, double *u, const double *f, int slot, int colour, int adjoint)
 {
-    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || h->checker || slot < 0 || slot > 1 || colour < 0 ||
+    if (bad_level(h, lv) || lv == h->nlev - 1 || !u || !f || h->checker || slot < 0 || slot >= MAXSLOT || colour < 0 ||
         colour > 1 || h->slot_motif[slot] < 0)
         return MG_EINVAL;
     Level &L = h->lev[lv];
@@ -2000,7 +2038,7 @@ const char *mg_strerror(int code)
 // ---------------------------------------------------------------------------
 int mg_debug_table_info(const mg_handle *h, int lv, int slot, int colour, int *info)
 {
-    if (bad_level(h, lv) || lv == h->nlev - 1 || slot < 0 || slot > 1 || colour < 0 || colour > 1 || !info)
+    if (bad_level(h, lv) || lv == h->nlev - 1 || slot < 0 || slot >= MAXSLOT || colour < 0 || colour > 1 || !info)
         return MG_EINVAL;
     const HostTable &t = h->lev[lv].htab[slot][colour];
     int maxc = 0, maxb = 0;
@@ -2087,7 +2125,7 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                         &red[7 * NT]};
     std::vector<LaneState<double>> st(NT);
     std::vector<double> rhs(NT), dl(NT), pt((size_t)NT * CH);
-    const int ns = h->slot_motif[1] >= 0 ? 2 : 1;
+    const int ns = nslots(h);
     for (int it = 0; it < nu; ++it)
         for (int k = 0; k < ns; ++k) {
             const int s = adj ? ns - 1 - k : k;

@@ -19,6 +19,9 @@ constexpr int COEF_PAD = CH + 2;
 // latency (the lane's serial chains and its gather batches are half as long)
 constexpr int SHORT_CH = 8;
 constexpr int SHORT_CH_MAXN = 1024; // levels with at most this many cells per axis
+// motif slots: the sweeps of one relaxation (three for 3D alternating-direction
+// zebra: lines along x, then y, then z)
+constexpr int MAXSLOT = 3;
 
 // Direction codes: d = 2*axis + (positive ? 1 : 0); the reverse is d ^ 1.
 __host__ __device__ inline int dir_axis(int d) { return d >> 1; }
@@ -218,11 +221,11 @@ struct TailLevel {
     int co;            // coefficient block (nine arrays of cs entries, as in Coef)
     int cs;
     int uoff, foff;    // the level's u and f (whole node arrays)
-    int chunk_off[2][2], block_off[2][2], wg_off[2][2], fac_off[2][2]; // [slot][colour] block tables
-    int nwg[2][2];
-    int rings[2][2];
-    int short_chunks;  // every chunk of the level has at most TAIL_SHORT_CH points
-    int onewave[2][2]; // every descriptor of the table has at most 64 chunks and 64 blocks
+    int chunk_off[MAXSLOT][2], block_off[MAXSLOT][2], wg_off[MAXSLOT][2], fac_off[MAXSLOT][2]; // [slot][colour]
+    int nwg[MAXSLOT][2];
+    int rings[MAXSLOT][2];
+    int short_chunks;        // every chunk of the level has at most TAIL_SHORT_CH points
+    int onewave[MAXSLOT][2]; // every descriptor of the table has at most 64 chunks and 64 blocks
 };
 
 template <typename T> struct TailPlan {

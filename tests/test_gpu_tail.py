@@ -48,6 +48,7 @@ CASES = [([64, 64], "tanh_wall", 3.0, "tweed", {}),
          ([96, 96], "tanh_wall", 2.0, "tweed", {"nu1": 1, "nu2": 3}),
          ([64, 64, 64], "tanh_wall", 2.5, "tweed", {}),
          ([32, 48, 32], "tanh_wall", 2.0, "zebra_z", {}),
+         ([64, 64, 64], "tanh_wall", 2.5, "adz", {}),
          ([256, 256], "tanh_wall", 3.0, "tweed", {"batch": 3})]
 
 

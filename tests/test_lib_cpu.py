@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol():
     assert pkg.capi().mg_strerror(pkg.MG_ENOTCONV).decode().startswith("not converged")
 
 
-def host_handle(n, kind, c, smoother, batch=1):
+def host_handle(n, kind, c, smoother, batch=1, sigma=None):
     lib = pkg.capi()
     g = pkg.mg_grid()
     g.dim = len(n)
@@ -46,9 +46,14 @@ def host_handle(n, kind, c, smoother, batch=1):
         g.L[a] = 1.0
     g.batch = batch
     st = pkg.mg_stretching()
+    bufs = []
     for a in range(len(n)):
         st.kind[a] = pkg.STRETCH[kind]
         st.param[a] = c
+        if sigma is not None and sigma[a] is not None:
+            buf = np.ascontiguousarray(sigma[a], dtype=np.float64)
+            bufs.append(buf)
+            st.sigma[a] = buf.ctypes.data_as(C.POINTER(C.c_double))
     o = pkg.mg_options()
     o.smoother = pkg.SMOOTHER[smoother]
     o.nu1 = o.nu2 = 2
@@ -104,7 +109,8 @@ EMU_CASES = [([16, 16], "tanh_wall", 2.0, "tweed"), ([64, 64], "tanh_wall", 3.0,
              ([16, 16], "tanh_wall", 2.0, "adz"), ([16, 16], "tanh_wall", 2.0, "alt_tw"),
              ([8, 8, 8], "tanh_wall", 2.0, "tweed"), ([16, 16, 16], "tanh_wall", 2.5, "tweed"),
              ([12, 8, 10], "tanh_wall", 2.5, "tweed"), ([4, 4, 4], "uniform", 0.0, "tweed"),
-             ([8, 8, 8], "tanh_wall", 2.0, "zebra_z"), ([512, 512], "tanh_wall", 3.0, "tweed"),
+             ([8, 8, 8], "tanh_wall", 2.0, "zebra_z"), ([8, 8, 8], "tanh_wall", 2.5, "adz"),
+             ([12, 8, 10], "sinh_centre", 3.0, "adz"), ([512, 512], "tanh_wall", 3.0, "tweed"),
              ([256, 256], "sinh_centre", 4.0, "wireframe")]
 
 
@@ -193,3 +199,52 @@ def test_full_size_tables(n, kind, c, sm, maxchunks):
         pts += info[5]
     assert pts == int(np.prod([k - 1 for k in n]))
     pkg.capi().mg_destroy(h)
+
+
+
+def _sigma(n, seed):
+    return np.exp(np.random.default_rng(seed).uniform(-3.0, 3.0, n))
+
+
+@pytest.mark.parametrize("n,kind,c,sm", [([64, 32], "tanh_wall", 2.5, "tweed"), ([32, 32], "sinh_centre", 3.0, "wireframe"),
+                                        ([16, 8, 12], "tanh_wall", 2.0, "adz"), ([256, 256], "tanh_wall", 3.0, "tweed")])
+def test_sigma_coefficients_and_sweep_match_oracle(n, kind, c, sm):
+    """Axis-wise conductivity (problem (CP) with sigma_aa = s_a(x_a)): the
+    library's coefficients on every level (flux form, series-averaged coarse
+    cells) and the kernel's per-lane sweep over its tables equal the oracle's."""
+    sig = [_sigma(k, 60 + a) for a, k in enumerate(n)]
+    rc, h = host_handle(n, kind, c, sm, sigma=sig)
+    assert rc == 0
+    xs = [O.coords(kind, c, k) for k in n]
+    H = O.Hierarchy(xs, sm, sigma=sig)
+    nl = C.c_int()
+    pkg.capi().mg_levels(h, C.byref(nl))
+    assert nl.value == H.nlev
+    for lv in range(H.nlev):
+        for a in range(len(n)):
+            m = H.level_n(lv)[a] + 1
+            x, lo, hi = np.zeros(m), np.zeros(m), np.zeros(m)
+            pkg.capi().mg_level_coefs(h, lv, a, x.ctypes.data_as(C.c_void_p), lo.ctypes.data_as(C.c_void_p),
+                                      hi.ctypes.data_as(C.c_void_p))
+            xo, loo, hio = H.level_coefs(lv, a)
+            assert rel_inf(lo, loo) < 1e-14 and rel_inf(hi, hio) < 1e-14, (lv, a)
+    shape = H.shape(0)
+    u = inputs.normal(shape, 7)
+    f = inputs.normal(shape, 8)
+    for adj in (0, 1):
+        Ho = O.Hierarchy(xs, sm, transpose=bool(adj), maxlev=1, sigma=sig)
+        ue = u.copy()
+        assert pkg.capi().mg_debug_host_smooth_layout(h, 0, ue.ctypes.data_as(C.c_void_p),
+                                                      f.ctypes.data_as(C.c_void_p), 1, adj) == 0
+        assert rel_inf(ue, Ho.smooth(u, f, 1)) < 1e-12
+    pkg.capi().mg_destroy(h)
+
+
+def test_sigma_rejects_nonpositive_values():
+    sig = [np.ones(16), np.ones(16)]
+    sig[1][3] = 0.0
+    assert host_handle([16, 16], "uniform", 0, "tweed", sigma=sig)[0] == pkg.MG_EINVAL
+    sig[1][3] = -1.0
+    assert host_handle([16, 16], "uniform", 0, "tweed", sigma=sig)[0] == pkg.MG_EINVAL
+    sig[1][3] = np.inf
+    assert host_handle([16, 16], "uniform", 0, "tweed", sigma=sig)[0] == pkg.MG_EINVAL
