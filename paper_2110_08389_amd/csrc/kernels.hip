@@ -13,6 +13,57 @@ namespace twmg {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// A node of the 3D split layout: its slot, the strides of x, y and z in its
+// plane, and how far it lies inside that plane's region (its own primed
+// coordinate below the smaller of the other two).  With margin >= 2 its six
+// axis neighbours share its plane; with margin >= 3 so does every node of its
+// 3 x 3 x 3 box (a diagonal step can tie the primed coordinates, and a tie
+// goes to the lower axis).
+struct P3 {
+    long long p;
+    long long sx, sy, sz;
+    int margin;
+};
+__device__ __forceinline__ P3 p3_at(const Dims &d, int i, int j, int l)
+{
+    const int ip = i < d.n[0] - i ? i : d.n[0] - i, jp = j < d.n[1] - j ? j : d.n[1] - j,
+              lp = l < d.n[2] - l ? l : d.n[2] - l;
+    const int pl = (ip <= jp && ip <= lp) ? 0 : (jp <= lp ? 1 : 2);
+    const int own = pl == 0 ? ip : (pl == 1 ? jp : lp);
+    const int o1 = pl == 0 ? jp : ip, o2 = pl == 2 ? jp : lp;
+    const long long S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1;
+    P3 q;
+    q.p = plane3_slot(d, pl, i, j, l);
+    q.sx = pl == 0 ? 1 : (pl == 1 ? S1 : S2);
+    q.sy = pl == 0 ? S0 : (pl == 1 ? 1 : S2 * S0);
+    q.sz = pl == 0 ? S0 * S1 : (pl == 1 ? S1 * S0 : 1);
+    q.margin = (o1 < o2 ? o1 : o2) - own;
+    return q;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double s[16];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) s[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        v = (lane < (int)(blockDim.x >> 6)) ? s[lane] : 0.0;
+        v = wave_max(v);
+    }
+    return v;
+}
+
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || b != b) ? __builtin_nan("") : fmax(a, b); }
+
 // slots of interior node (i, j, l) and of its neighbours x-, x+, y-, y+, z-, z+
 template <int DIM> struct Stencil {
     long long p, nb[2 * DIM];
@@ -26,6 +77,26 @@ template <int DIM> __device__ __forceinline__ Stencil<DIM> stencil_at(const Dims
         s.nb[1] = nidx(d, i + 1, j, 0);
         s.nb[2] = nidx(d, i, j - 1, 0);
         s.nb[3] = nidx(d, i, j + 1, 0);
+    } else if (DIM == 3 && d.layout != LAYOUT_ROW) {
+        // the slots of the 3D split layout: fixed offsets in the node's plane
+        // unless it lies within 2 of the plane's border
+        const P3 q = p3_at(d, i, j, l);
+        s.p = q.p;
+        if (q.margin >= 2) {
+            s.nb[0] = q.p - q.sx;
+            s.nb[1] = q.p + q.sx;
+            s.nb[2] = q.p - q.sy;
+            s.nb[3] = q.p + q.sy;
+            s.nb[2 * DIM - 2] = q.p - q.sz;
+            s.nb[2 * DIM - 1] = q.p + q.sz;
+        } else {
+            s.nb[0] = nidx(d, i - 1, j, l);
+            s.nb[1] = nidx(d, i + 1, j, l);
+            s.nb[2] = nidx(d, i, j - 1, l);
+            s.nb[3] = nidx(d, i, j + 1, l);
+            s.nb[2 * DIM - 2] = nidx(d, i, j, l - 1);
+            s.nb[2 * DIM - 1] = nidx(d, i, j, l + 1);
+        }
     } else {
         s.p = i + j * d.st[1] + (DIM == 3 ? l * d.st[2] : 0);
 #pragma unroll
@@ -64,22 +135,53 @@ __device__ __forceinline__ int nrows(const Dims &d, int DIM)
 }
 
 // Storage-order traversal of a node array, so that consecutive threads touch
-// consecutive slots: LAYOUT_ROW has the rows (j, l) of nx+1 nodes; a split
+// consecutive slots: LAYOUT_ROW has the rows (j, l) of nx+1 nodes; a 2D split
 // layout has the ny+1 rows of plane R, then the nx+1 columns (ny+1 nodes) of
-// plane C.
+// plane C; the 3D split layout has the (j, l) rows of plane 0, the (i, l)
+// rows of plane 1 and the (i, j) rows of plane 2.
 __device__ __forceinline__ int lrows(const Dims &d, int DIM)
 {
+    if (d.layout == LAYOUT_TWEED3)
+        return (d.n[1] + 1) * (d.n[2] + 1) + (d.n[0] + 1) * (d.n[2] + 1) + (d.n[0] + 1) * (d.n[1] + 1);
     return d.layout == LAYOUT_ROW ? nrows(d, DIM) : (d.n[1] + 1) + (d.n[0] + 1);
 }
 __device__ __forceinline__ int lrow_len(const Dims &d, int row)
 {
+    if (d.layout == LAYOUT_TWEED3) {
+        const int r0 = (d.n[1] + 1) * (d.n[2] + 1), r1 = (d.n[0] + 1) * (d.n[2] + 1);
+        return row < r0 ? d.n[0] + 1 : (row < r0 + r1 ? d.n[1] + 1 : d.n[2] + 1);
+    }
     return (d.layout != LAYOUT_ROW && row > d.n[1]) ? d.n[1] + 1 : d.n[0] + 1;
 }
 // node q of row `row`: its coordinates and slot; false when the node is kept
-// in the other plane (each node is visited exactly once over all rows)
+// in another plane (each node is visited exactly once over all rows)
 template <int DIM>
 __device__ __forceinline__ bool lnode(const Dims &d, int row, int q, int &i, int &j, int &l, long long &p)
 {
+    if (DIM == 3 && d.layout == LAYOUT_TWEED3) {
+        const int r0 = (d.n[1] + 1) * (d.n[2] + 1), r1 = (d.n[0] + 1) * (d.n[2] + 1);
+        int pl;
+        if (row < r0) {
+            pl = 0;
+            i = q;
+            j = row % (d.n[1] + 1);
+            l = row / (d.n[1] + 1);
+        } else if (row < r0 + r1) {
+            pl = 1;
+            const int rr = row - r0;
+            j = q;
+            i = rr % (d.n[0] + 1);
+            l = rr / (d.n[0] + 1);
+        } else {
+            pl = 2;
+            const int rr = row - r0 - r1;
+            l = q;
+            i = rr % (d.n[0] + 1);
+            j = rr / (d.n[0] + 1);
+        }
+        p = plane3_slot(d, pl, i, j, l);
+        return plane3(d, i, j, l) == pl;
+    }
     if (d.layout == LAYOUT_ROW) {
         j = row % (d.n[1] + 1);
         l = DIM == 3 ? row / (d.n[1] + 1) : 0;
@@ -102,8 +204,13 @@ __device__ __forceinline__ bool lnode(const Dims &d, int row, int q, int &i, int
 
 static int lrow_grid(const Dims &d)
 {
-    const int r = d.layout == LAYOUT_ROW ? (d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1) : d.n[0] + d.n[1] + 2;
-    return r < 65535 ? r : 65535;
+    long long r;
+    if (d.layout == LAYOUT_TWEED3)
+        r = (long long)(d.n[1] + 1) * (d.n[2] + 1) + (long long)(d.n[0] + 1) * (d.n[2] + 1) +
+            (long long)(d.n[0] + 1) * (d.n[1] + 1);
+    else
+        r = d.layout == LAYOUT_ROW ? (long long)(d.n[1] + 1) * (d.dim == 3 ? d.n[2] + 1 : 1) : d.n[0] + d.n[1] + 2;
+    return r < 65535 ? (int)r : 65535;
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,24 +1136,6 @@ __global__ void __launch_bounds__(256) k_prolong_tile(Dims fd, Dims cd, const T 
     }
 }
 
-template <typename T>
-hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
-                                    T *uc, int batch, hipStream_t s)
-{
-    if (fd.dim == 2) {
-        dim3 tiles(((cd.n[0] - 1 + 15) / 16) * ((cd.n[1] - 1 + 15) / 16), batch);
-        hipLaunchKernelGGL((k_restrict_tile<T>), tiles, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
-        return hipGetLastError();
-    }
-    dim3 grid(row_grid(cd), batch);
-    hipLaunchKernelGGL((k_residual_restrict<T, 3>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Fused bilinear/trilinear prolongation + update (Section 4, fused step 5):
-// u += P e_c in index space; e_c's boundary entries are zero.
-// ---------------------------------------------------------------------------
 // interpolated coarse correction at fine interior node (i, j, l): weights 1
 // (even index) or 1/2 + 1/2 (odd index) per axis
 template <typename T, int DIM>
@@ -1054,7 +1143,19 @@ __device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int 
 {
     const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
     const int K0 = l >> 1, K1 = (l + 1) >> 1;
-    auto cval = [&](int I, int J, int K) -> T { return eb[nidx(cd, I, J, K)]; };
+    // 3D split coarse level: the 2 x 2 x 2 coarse box at fixed offsets in the
+    // plane of its first corner when that corner lies 3 or more inside it
+    bool fast = false;
+    P3 q0{0, 0, 0, 0, 0};
+    if (DIM == 3 && cd.layout == LAYOUT_TWEED3) {
+        q0 = p3_at(cd, I0, J0, K0);
+        fast = q0.margin >= 3;
+    }
+    auto cval = [&](int I, int J, int K) -> T {
+        if (DIM == 3 && cd.layout == LAYOUT_TWEED3 && fast)
+            return eb[q0.p + (I - I0) * q0.sx + (J - J0) * q0.sy + (K - K0) * q0.sz];
+        return eb[nidx(cd, I, J, K)];
+    };
     T pl[2];
 #pragma unroll
     for (int kk = 0; kk < (DIM == 3 ? 2 : 1); ++kk) {
@@ -1067,23 +1168,366 @@ __device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int 
     return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
 }
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_prolong_add(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
+// the axes of plane PL: fast axis PL, then (y, z) for 0, (x, z) for 1, (x, y) for 2
+template <int PL> struct PlaneAxes {
+    static constexpr int F = PL, A = PL == 0 ? 1 : 0, B = PL == 2 ? 1 : 2;
+};
+template <int PL> __host__ __device__ __forceinline__ int ptiles(const Dims &d)
 {
-    T *ub = u + (long long)blockIdx.y * fd.bs;
-    const T *eb = ec + (long long)blockIdx.y * cd.bs;
-    const int rows = lrows(fd, DIM);
-    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int len = lrow_len(fd, row);
-        for (int q = threadIdx.x; q < len; q += blockDim.x) {
-            int i, j, l;
-            long long p;
-            if (!lnode<DIM>(fd, row, q, i, j, l, p) || !interior<DIM>(fd, i, j, l)) continue;
-            ub[p] += prolong_at<T, DIM>(cd, eb, i, j, l);
+    using X = PlaneAxes<PL>;
+    return ((d.n[X::F] + 16) / 16) * ((d.n[X::A] + 4) / 4) * ((d.n[X::B] + 4) / 4);
+}
+__host__ __device__ __forceinline__ int tiles3(const Dims &d)
+{
+    return d.layout == LAYOUT_TWEED3 ? ptiles<0>(d) + ptiles<1>(d) + ptiles<2>(d) : ptiles<0>(d);
+}
+template <int PL> __device__ __forceinline__ int slot_in_plane(const Dims &d, int i, int j, int l)
+{
+    const int S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1, nn = (int)d.nn;
+    if (PL == 0) return i + S0 * (j + S1 * l);
+    if (PL == 1) return nn + j + S1 * (i + S0 * l);
+    return 2 * nn + l + S2 * (i + S0 * j);
+}
+
+// Node threadIdx.x of tile t of plane PL: op(i, j, l, slot) when the node is
+// in the grid and kept in plane PL.  A tile whose 8 corners all lie in other
+// planes, and that does not straddle a centre line n/2, is skipped whole:
+// away from the centre lines the primed coordinates are monotone along each
+// axis inside a tile, so the plane's region (an intersection of half-spaces
+// in them) meets the tile only if it holds a corner.
+template <int PL, typename Op>
+__device__ __forceinline__ void tile3_plane(const Dims &d, int t, Op &&op)
+{
+    using X = PlaneAxes<PL>;
+    const int tf = (d.n[X::F] + 16) / 16, ta = (d.n[X::A] + 4) / 4;
+    const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * 4;
+    if (d.layout == LAYOUT_TWEED3) {
+        const int nf = d.n[X::F], na = d.n[X::A], nb = d.n[X::B];
+        const int f1 = min(f0 + 15, nf), a1 = min(a0 + 3, na), b1 = min(b0 + 3, nb);
+        bool any = (f0 < nf / 2 && f1 > nf / 2) || (a0 < na / 2 && a1 > na / 2) || (b0 < nb / 2 && b1 > nb / 2);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int c[3];
+            c[X::F] = (k & 1) ? f1 : f0;
+            c[X::A] = (k & 2) ? a1 : a0;
+            c[X::B] = (k & 4) ? b1 : b0;
+            any = any || plane3(d, c[0], c[1], c[2]) == PL;
         }
+        if (!any) return;
+    }
+    const int q = threadIdx.x;
+    int c[3];
+    c[X::F] = f0 + (q & 15);
+    c[X::A] = a0 + ((q >> 4) & 3);
+    c[X::B] = b0 + (q >> 6);
+    if (c[0] > d.n[0] || c[1] > d.n[1] || c[2] > d.n[2]) return;
+    if (d.layout == LAYOUT_TWEED3 && plane3(d, c[0], c[1], c[2]) != PL) return;
+    op(c[0], c[1], c[2], slot_in_plane<PL>(d, c[0], c[1], c[2]));
+}
+
+// 3D stencil kernels walk the nodes of every plane of the layout in tiles of
+// 16 along the plane's fast axis by 4 x 4 across it (256 nodes, one per
+// thread: a wavefront reads four whole 128-byte runs).  A tile handles only
+// the nodes kept in its plane, so the three tile families visit every node
+// once; the row-major layout has plane 0 only.  The plane is uniform per
+// workgroup and a template argument below the branch, so no coordinate is
+// picked by a run-time axis index.
+template <typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int t, Op &&op)
+{
+    const int t0 = ptiles<0>(d);
+    if (t < t0) {
+        tile3_plane<0>(d, t, op);
+        return;
+    }
+    t -= t0;
+    const int t1 = ptiles<1>(d);
+    if (t < t1)
+        tile3_plane<1>(d, t, op);
+    else
+        tile3_plane<2>(d, t - t1, op);
+}
+__device__ __forceinline__ int tile3_index(int it, int nt) { return (int)gridDim.x == nt ? xcd_tile(it, nt) : it; }
+
+// 32-bit slot of a 3D node and its plane's strides (every per-problem array
+// is below 2^31 entries, which set-up checks); margin as for P3.  For the
+// row-major layout the strides are the row-major ones and margin is large.
+struct P3i {
+    int p, sx, sy, sz, margin;
+};
+__device__ __forceinline__ P3i p3i_at(const Dims &d, int i, int j, int l)
+{
+    const int S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1;
+    P3i q;
+    if (d.layout != LAYOUT_TWEED3) {
+        q.p = i + S0 * (j + S1 * l);
+        q.sx = 1;
+        q.sy = S0;
+        q.sz = S0 * S1;
+        q.margin = 1 << 20;
+        return q;
+    }
+    const int ip = min(i, d.n[0] - i), jp = min(j, d.n[1] - j), lp = min(l, d.n[2] - l);
+    const int pl = (ip <= jp && ip <= lp) ? 0 : (jp <= lp ? 1 : 2);
+    const int nn = (int)d.nn;
+    if (pl == 0) {
+        q.p = i + S0 * (j + S1 * l);
+        q.sx = 1;
+        q.sy = S0;
+        q.sz = S0 * S1;
+        q.margin = min(jp, lp) - ip;
+    } else if (pl == 1) {
+        q.p = nn + j + S1 * (i + S0 * l);
+        q.sx = S1;
+        q.sy = 1;
+        q.sz = S1 * S0;
+        q.margin = min(ip, lp) - jp;
+    } else {
+        q.p = 2 * nn + l + S2 * (i + S0 * j);
+        q.sx = S2;
+        q.sy = S2 * S0;
+        q.sz = 1;
+        q.margin = min(ip, jp) - lp;
+    }
+    return q;
+}
+__device__ __forceinline__ int slot3(const Dims &d, int i, int j, int l) { return p3i_at(d, i, j, l).p; }
+
+// the slots a 7-point defect at (i, j, l) reads: itself, x-, x+, y-, y+, z-, z+
+struct Nb7 {
+    int p, nb[6];
+};
+__device__ __forceinline__ Nb7 nb7_at(const Dims &d, int i, int j, int l)
+{
+    const P3i q = p3i_at(d, i, j, l);
+    Nb7 r;
+    r.p = q.p;
+    if (q.margin >= 2) {
+        r.nb[0] = q.p - q.sx;
+        r.nb[1] = q.p + q.sx;
+        r.nb[2] = q.p - q.sy;
+        r.nb[3] = q.p + q.sy;
+        r.nb[4] = q.p - q.sz;
+        r.nb[5] = q.p + q.sz;
+    } else {
+        r.nb[0] = slot3(d, i - 1, j, l);
+        r.nb[1] = slot3(d, i + 1, j, l);
+        r.nb[2] = slot3(d, i, j - 1, l);
+        r.nb[3] = slot3(d, i, j + 1, l);
+        r.nb[4] = slot3(d, i, j, l - 1);
+        r.nb[5] = slot3(d, i, j, l + 1);
+    }
+    return r;
+}
+
+// Defects of NB nodes at once: every load is issued before any arithmetic.
+// Nodes with in[k] false give 0 (their loads are clamped to node (1, 1, 1)).
+// Same summation order as defect_at.
+template <typename T, int NB>
+__device__ __forceinline__ void defects3(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                         const T *__restrict__ fb, const int (&i)[NB], const int (&j)[NB],
+                                         const int (&l)[NB], const bool (&in)[NB], T (&out)[NB])
+{
+    T uv[NB][7], fv[NB], c[NB][9];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int ic = in[k] ? i[k] : 1, jc = in[k] ? j[k] : 1, lc = in[k] ? l[k] : 1;
+        const Nb7 s = nb7_at(d, ic, jc, lc);
+        uv[k][0] = ub[s.p];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) uv[k][m + 1] = ub[s.nb[m]];
+        fv[k] = fb[s.p];
+        c[k][0] = cf.lo[0][ic];
+        c[k][1] = cf.hi[0][ic];
+        c[k][2] = cf.lo[1][jc];
+        c[k][3] = cf.hi[1][jc];
+        c[k][4] = cf.lo[2][lc];
+        c[k][5] = cf.hi[2][lc];
+        c[k][6] = cf.dg[0][ic];
+        c[k][7] = cf.dg[1][jc];
+        c[k][8] = cf.dg[2][lc];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        T sum = c[k][0] * uv[k][1] + c[k][1] * uv[k][2];
+        sum += c[k][2] * uv[k][3] + c[k][3] * uv[k][4];
+        T dg = c[k][6] + c[k][7];
+        sum += c[k][4] * uv[k][5] + c[k][5] * uv[k][6];
+        dg += c[k][8];
+        out[k] = in[k] ? fv[k] - (sum + dg * uv[k][0]) : T(0);
     }
 }
 
+// defect d = f - L u of every node (0 on boundary nodes) into r (layout of d)
+template <typename T>
+__global__ void __launch_bounds__(256) k_residual3(Dims d, Coef<T> cf, const T *__restrict__ u,
+                                                   const T *__restrict__ f, T *__restrict__ r)
+{
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int nt = tiles3(d);
+    for (int it = blockIdx.x; it < nt; it += gridDim.x)
+        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int sl) {
+            const int ia[1] = {i}, ja[1] = {j}, la[1] = {l};
+            const bool in[1] = {interior<3>(d, i, j, l)};
+            T dv[1];
+            defects3<T, 1>(d, cf, u + boff, f + boff, ia, ja, la, in, dv);
+            r[boff + sl] = dv[0];
+        });
+}
+
+// per-workgroup maximum of |f - L u| over interior nodes (optionally the
+// defect rounded to FP32 into r32)
+template <typename T, bool TO32>
+__global__ void __launch_bounds__(256) k_resnorm3(Dims d, Coef<T> cf, const T *__restrict__ u,
+                                                  const T *__restrict__ f, float *__restrict__ r32,
+                                                  double *__restrict__ partial)
+{
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int nt = tiles3(d);
+    double m = 0.0;
+    bool nan = false;
+    for (int it = blockIdx.x; it < nt; it += gridDim.x)
+        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int sl) {
+            const int ia[1] = {i}, ja[1] = {j}, la[1] = {l};
+            const bool in[1] = {interior<3>(d, i, j, l)};
+            T dv[1];
+            defects3<T, 1>(d, cf, u + boff, f + boff, ia, ja, la, in, dv);
+            if (TO32) r32[boff + sl] = (float)dv[0];
+            const double a = fabs((double)dv[0]);
+            nan = nan || (a != a);
+            m = fmax(m, a);
+        });
+    if (nan) m = __builtin_inf();
+    m = block_max(m);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
+}
+
+// interpolated coarse correction (as prolong_at) with 32-bit slots: the
+// 2 x 2 x 2 coarse box at fixed offsets in the plane of its first corner when
+// that corner lies 3 or more inside it
+template <typename T>
+__device__ __forceinline__ T prolong3_at(const Dims &cd, const T *eb, int i, int j, int l)
+{
+    const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
+    const int K0 = l >> 1, K1 = (l + 1) >> 1;
+    const P3i q0 = p3i_at(cd, I0, J0, K0);
+    const bool fast = q0.margin >= 3;
+    auto cval = [&](int I, int J, int K) -> T {
+        return eb[fast ? q0.p + (I - I0) * q0.sx + (J - J0) * q0.sy + (K - K0) * q0.sz : slot3(cd, I, J, K)];
+    };
+    T pl[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const int K = kk ? K1 : K0;
+        const T r0 = (I0 == I1) ? cval(I0, J0, K) : T(0.5) * (cval(I0, J0, K) + cval(I1, J0, K));
+        const T r1 = (I0 == I1) ? cval(I0, J1, K) : T(0.5) * (cval(I0, J1, K) + cval(I1, J1, K));
+        pl[kk] = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
+    }
+    return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
+}
+
+// u += P e_c at fine interior nodes
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong3(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
+{
+    T *ub = u + (long long)blockIdx.y * fd.bs;
+    const T *eb = ec + (long long)blockIdx.y * cd.bs;
+    const int nt = tiles3(fd);
+    for (int it = blockIdx.x; it < nt; it += gridDim.x)
+        tile3_visit(fd, tile3_index(it, nt), [&](int i, int j, int l, int p) {
+            if (interior<3>(fd, i, j, l)) ub[p] += prolong3_at<T>(cd, eb, i, j, l);
+        });
+}
+
+// full weighting of the defect array dr (fine layout, 0 on boundary nodes)
+// at coarse interior nodes, over coarse tiles; clears the coarse correction.
+// Same weights and summation order as restrict_at.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fw_restrict3(Dims fd, Dims cd, const T *__restrict__ dr, T *__restrict__ fc,
+                                                      T *__restrict__ uc)
+{
+    const T *db = dr + (long long)blockIdx.y * fd.bs;
+    const long long cboff = (long long)blockIdx.y * cd.bs;
+    const int nt = tiles3(cd);
+    for (int it = blockIdx.x; it < nt; it += gridDim.x)
+        tile3_visit(cd, tile3_index(it, nt), [&](int I, int J, int K, int pcs) {
+            if (!interior<3>(cd, I, J, K)) return;
+            // the fine 3 x 3 x 3 box at fixed offsets in the plane of its
+            // centre when that centre lies 3 or more inside it
+            const P3i pc = p3i_at(fd, 2 * I, 2 * J, 2 * K);
+            const bool fast = pc.margin >= 3;
+            T v[27];
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                for (int b = -1; b <= 1; ++b)
+#pragma unroll
+                    for (int a = -1; a <= 1; ++a)
+                        v[(cz + 1) * 9 + (b + 1) * 3 + (a + 1)] =
+                            db[fast ? pc.p + a * pc.sx + b * pc.sy + cz * pc.sz
+                                    : slot3(fd, 2 * I + a, 2 * J + b, 2 * K + cz)];
+            __builtin_amdgcn_sched_barrier(0);
+            const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+            T acc = 0;
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+#pragma unroll
+                for (int b = -1; b <= 1; ++b) {
+                    T rowacc = 0;
+#pragma unroll
+                    for (int a = -1; a <= 1; ++a) rowacc += w3[a + 1] * v[(cz + 1) * 9 + (b + 1) * 3 + (a + 1)];
+                    acc += w3[cz + 1] * w3[b + 1] * rowacc;
+                }
+            }
+            fc[cboff + pcs] = acc;
+            uc[cboff + pcs] = T(0);
+        });
+}
+
+// u += e at interior nodes (FP64 update of iterative refinement), 3D tiles
+__global__ void __launch_bounds__(256) k_ir_update3(Dims d, double *__restrict__ u, const float *__restrict__ e)
+{
+    const long long boff = (long long)blockIdx.y * d.bs;
+    const int nt = tiles3(d);
+    for (int it = blockIdx.x; it < nt; it += gridDim.x)
+        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int p) {
+            if (interior<3>(d, i, j, l)) u[boff + p] += (double)e[boff + p];
+        });
+}
+
+// workgroups of a 3D tile launch: one per tile up to 65535
+static int tile3_grid(const Dims &d)
+{
+    const int nt = tiles3(d);
+    return nt < 65535 ? nt : 65535;
+}
+
+template <typename T>
+hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
+                                    T *uc, int batch, hipStream_t s, T *dscr)
+{
+    if (fd.dim == 2) {
+        dim3 tiles(((cd.n[0] - 1 + 15) / 16) * ((cd.n[1] - 1 + 15) / 16), batch);
+        hipLaunchKernelGGL((k_restrict_tile<T>), tiles, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+        return hipGetLastError();
+    }
+    if (fd.layout == LAYOUT_TWEED3) {
+        // each fine defect once, into the scratch array (fine layout), then
+        // the 27-point weighting from it
+        if (!dscr) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_residual3<T>), dim3(tile3_grid(fd), batch), dim3(256), 0, s, fd, c, u, f, dscr);
+        hipLaunchKernelGGL((k_fw_restrict3<T>), dim3(tile3_grid(cd), batch), dim3(256), 0, s, fd, cd, dscr, fc, uc);
+        return hipGetLastError();
+    }
+    dim3 grid(row_grid(cd), batch);
+    hipLaunchKernelGGL((k_residual_restrict<T, 3>), grid, dim3(256), 0, s, fd, cd, c, u, f, fc, uc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused bilinear/trilinear prolongation + update (Section 4, fused step 5):
+// u += P e_c in index space; e_c's boundary entries are zero.
+// ---------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s)
 {
@@ -1092,8 +1536,7 @@ hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u,
         hipLaunchKernelGGL((k_prolong_tile<T>), tiles, dim3(256), 0, s, fd, cd, ec, u);
         return hipGetLastError();
     }
-    dim3 grid(row_grid(fd), batch);
-    hipLaunchKernelGGL((k_prolong_add<T, 3>), grid, dim3(256), 0, s, fd, cd, ec, u);
+    hipLaunchKernelGGL((k_prolong3<T>), dim3(tile3_grid(fd), batch), dim3(256), 0, s, fd, cd, ec, u);
     return hipGetLastError();
 }
 
@@ -1374,55 +1817,6 @@ hipError_t launch_tail_cycle(const TailPlan<T> &p, T *u, const T *f, int batch, 
 // independent, so the result is bitwise reproducible.  Optionally writes the
 // defect rounded to FP32 (iterative refinement's right-hand side).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ double block_max(double v)
-{
-    __shared__ double s[16];
-    v = wave_max(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) s[wv] = v;
-    __syncthreads();
-    if (wv == 0) {
-        v = (lane < (int)(blockDim.x >> 6)) ? s[lane] : 0.0;
-        v = wave_max(v);
-    }
-    return v;
-}
-
-__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || b != b) ? __builtin_nan("") : fmax(a, b); }
-
-template <typename T, int DIM, bool TO32>
-__global__ void __launch_bounds__(256) k_resnorm(Dims d, Coef<T> cf, const T *__restrict__ u, const T *__restrict__ f,
-                                                 float *__restrict__ r32, double *__restrict__ partial)
-{
-    const long long boff = (long long)blockIdx.y * d.bs;
-    const int rows = lrows(d, DIM);
-    double m = 0.0;
-    bool nan = false;
-    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int len = lrow_len(d, row);
-        for (int q = threadIdx.x; q < len; q += blockDim.x) {
-            int i, j, l;
-            long long p;
-            if (!lnode<DIM>(d, row, q, i, j, l, p)) continue;
-            T r = 0;
-            if (interior<DIM>(d, i, j, l)) r = defect_at<T, DIM>(d, cf, u + boff, f + boff, i, j, l);
-            if (TO32) r32[boff + p] = (float)r;
-            const double a = fabs((double)r);
-            nan = nan || (a != a);
-            m = fmax(m, a);
-        }
-    }
-    if (nan) m = __builtin_inf();
-    m = block_max(m);
-    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
-}
 
 // 2D tiled version: 32 x 32 nodes per tile, u staged with a one-node halo;
 // the workgroups stride over the tiles of their problem
@@ -1524,7 +1918,8 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
         if (gx > nt) gx = nt;
         hipLaunchKernelGGL((k_resnorm_tile<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     } else {
-        hipLaunchKernelGGL((k_resnorm<T, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
+        if (gx > tiles3(d)) gx = tiles3(d);
+        hipLaunchKernelGGL((k_resnorm3<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
     return hipGetLastError();
@@ -1543,7 +1938,8 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
         hipLaunchKernelGGL((k_resnorm_tile<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32,
                            partial);
     } else {
-        hipLaunchKernelGGL((k_resnorm<double, 3, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
+        if (gx > tiles3(d)) gx = tiles3(d);
+        hipLaunchKernelGGL((k_resnorm3<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
     return hipGetLastError();
@@ -1600,7 +1996,8 @@ hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const do
         hipLaunchKernelGGL((k_resnorm_tile<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     } else {
-        hipLaunchKernelGGL((k_resnorm<double, 3, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
+        if (gx > tiles3(d)) gx = tiles3(d);
+        hipLaunchKernelGGL((k_resnorm3<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     }
     // one workgroup over all problems' partial maxima: the batch's maximum
@@ -1628,7 +2025,7 @@ hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch,
 {
     dim3 grid(row_grid(d), batch);
     if (d.dim == 2) hipLaunchKernelGGL((k_ir_update<2>), grid, dim3(256), 0, s, d, u, e);
-    else hipLaunchKernelGGL((k_ir_update<3>), grid, dim3(256), 0, s, d, u, e);
+    else hipLaunchKernelGGL(k_ir_update3, dim3(tile3_grid(d), batch), dim3(256), 0, s, d, u, e);
     return hipGetLastError();
 }
 
@@ -1708,11 +2105,34 @@ __global__ void __launch_bounds__(256) k_convert(Dims d, const T *__restrict__ s
     }
 }
 
+// the same for the 3D split layout, one node per thread in row-major order
+// (the row-major side is contiguous; planes 1 and 2 are written or read
+// along their strided axis)
+template <typename T, bool TO_SPLIT>
+__global__ void __launch_bounds__(256) k_convert3(Dims d, const T *__restrict__ src, T *__restrict__ dst)
+{
+    const long long rb = (long long)blockIdx.y * d.nn, sb = (long long)blockIdx.y * d.bs;
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < d.nn; p += (long long)gridDim.x * 256) {
+        const int i = (int)(p % d.st[1]), j = (int)((p / d.st[1]) % (d.n[1] + 1)), l = (int)(p / d.st[2]);
+        const long long q = nidx(d, i, j, l);
+        if (TO_SPLIT) dst[sb + q] = src[rb + p];
+        else dst[rb + p] = src[sb + q];
+    }
+}
+
 template <typename T>
 hipError_t launch_convert(const Dims &d, const T *src, T *dst, int to_split, int batch, hipStream_t s)
 {
     if (d.layout == LAYOUT_ROW)
         return hipMemcpyAsync(dst, src, sizeof(T) * (size_t)d.nn * batch, hipMemcpyDeviceToDevice, s);
+    if (d.layout == LAYOUT_TWEED3) {
+        long long nb = (d.nn + 255) / 256;
+        if (nb > 16384) nb = 16384;
+        const dim3 grid((unsigned)nb, batch);
+        if (to_split) hipLaunchKernelGGL((k_convert3<T, true>), grid, dim3(256), 0, s, d, src, dst);
+        else hipLaunchKernelGGL((k_convert3<T, false>), grid, dim3(256), 0, s, d, src, dst);
+        return hipGetLastError();
+    }
     dim3 grid((d.n[0] + 32) / 32, (d.n[1] + 32) / 32, batch);
     if (to_split) hipLaunchKernelGGL((k_convert<T, true>), grid, dim3(256), 0, s, d, src, dst);
     else hipLaunchKernelGGL((k_convert<T, false>), grid, dim3(256), 0, s, d, src, dst);
@@ -1789,7 +2209,7 @@ hipError_t launch_bc_grad(const Dims &d, const Coef<double> &fwd, const double *
                                            int, hipStream_t);                                                         \
     template hipError_t launch_convert<T>(const Dims &, const T *, T *, int, int, hipStream_t);                      \
     template hipError_t launch_residual_restrict<T>(const Dims &, const Dims &, const Coef<T> &, const T *,          \
-                                                    const T *, T *, T *, int, hipStream_t);                           \
+                                                    const T *, T *, T *, int, hipStream_t, T *);                      \
     template hipError_t launch_prolong_add<T>(const Dims &, const Dims &, const T *, T *, int, hipStream_t);         \
     template hipError_t launch_coarse_solve<T>(const Dims &, const Coef<T> &, T *, const T *, const T *, int, int,   \
                                                hipStream_t);                                                          \

@@ -93,6 +93,7 @@ template <typename T, int C = CH> struct LaneState {
 __host__ __device__ __forceinline__ int slot32(const Dims &d, int i, int j, int l)
 {
     if (d.layout == LAYOUT_ROW) return i + j * (int)d.st[1] + l * (int)d.st[2];
+    if (d.layout == LAYOUT_TWEED3) return (int)plane3_slot(d, plane3(d, i, j, l), i, j, l);
     return col_plane(d, i, j) ? (int)d.nn + j + i * (d.n[1] + 1) : i + j * (int)d.st[1];
 }
 
@@ -105,6 +106,38 @@ template <int DIM> struct NbSlots {
 template <int DIM> __host__ __device__ __forceinline__ NbSlots<DIM> nb_slots(const Dims &d, int i, int j, int l)
 {
     NbSlots<DIM> s;
+    if (DIM == 3 && d.layout == LAYOUT_TWEED3) {
+        // a node whose own primed coordinate is at least 2 below the other two
+        // has all six neighbours in its plane, at that plane's fixed offsets;
+        // nearer the planes' borders every slot is computed
+        const int ip = i < d.n[0] - i ? i : d.n[0] - i, jp = j < d.n[1] - j ? j : d.n[1] - j,
+                  lp = l < d.n[2] - l ? l : d.n[2] - l;
+        const int pl = (ip <= jp && ip <= lp) ? 0 : (jp <= lp ? 1 : 2);
+        const int own = pl == 0 ? ip : (pl == 1 ? jp : lp);
+        const int o1 = pl == 0 ? jp : ip, o2 = pl == 2 ? jp : lp;
+        s.p = (int)plane3_slot(d, pl, i, j, l);
+        if (own + 2 <= o1 && own + 2 <= o2) {
+            const int S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1;
+            // strides of x, y, z in the node's plane
+            const int sx = pl == 0 ? 1 : (pl == 1 ? S1 : S2);
+            const int sy = pl == 0 ? S0 : (pl == 1 ? 1 : S2 * S0);
+            const int sz = pl == 0 ? S0 * S1 : (pl == 1 ? S1 * S0 : 1);
+            s.nb[0] = s.p - sx;
+            s.nb[1] = s.p + sx;
+            s.nb[2] = s.p - sy;
+            s.nb[3] = s.p + sy;
+            s.nb[2 * DIM - 2] = s.p - sz;
+            s.nb[2 * DIM - 1] = s.p + sz;
+        } else {
+            s.nb[0] = slot32(d, i - 1, j, l);
+            s.nb[1] = slot32(d, i + 1, j, l);
+            s.nb[2] = slot32(d, i, j - 1, l);
+            s.nb[3] = slot32(d, i, j + 1, l);
+            s.nb[2 * DIM - 2] = slot32(d, i, j, l - 1);
+            s.nb[2 * DIM - 1] = slot32(d, i, j, l + 1);
+        }
+        return s;
+    }
     if (DIM == 3 || d.layout == LAYOUT_ROW) {
         const int S1 = (int)d.st[1], S2 = (int)d.st[2];
         s.p = i + j * S1 + (DIM == 3 ? l * S2 : 0);
@@ -444,7 +477,6 @@ __host__ __device__ __forceinline__ void sweep_phase1_coefs(const Dims &d, const
     const uint8_t fl = ch.flags;
     const bool hp = fl & CF_PREV, hn = fl & CF_NEXT, nd = fl & CF_NEXT_DIRECT;
     const int c0x = ch.c0[0], c0y = ch.c0[1], c0z = (DIM == 3) ? ch.c0[2] : 0;
-    const int cax = (ax == 0) ? c0x : ((ax == 1) ? c0y : c0z);
     const int ex = (ax == 0) ? sg : 0, ey = (ax == 1) ? sg : 0, ez = (ax == 2) ? sg : 0;
     st.L = L;
     st.prev = ch.prev;

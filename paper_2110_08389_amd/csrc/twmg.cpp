@@ -818,6 +818,7 @@ struct mg_handle {
     DevPool pool;
     size_t ws_bytes = 0;
     char *ws = nullptr;
+    char *dscr = nullptr; // 3D split levels: defect scratch of the restriction (one fine array, FP64 or FP32)
     bool ws_owned = false;
     // coarse-level kernel: levels tail_lv .. nlev-1 run in one workgroup per problem
     int tail_lv = -1;
@@ -864,6 +865,15 @@ size_t workspace_layout(mg_handle *h, bool assign)
             L.u32 = (float *)(h->ws + ou32);
             L.f32 = (float *)(h->ws + of32);
         }
+    }
+    // the restriction from a 3D split level runs in two passes through a
+    // defect array of that level
+    size_t dmax = 0;
+    for (int l = 0; l + 1 < h->nlev; ++l)
+        if (h->lev[l].d.layout == LAYOUT_TWEED3) dmax = std::max(dmax, (size_t)h->lev[l].d.bs * B * sizeof(double));
+    if (dmax) {
+        const size_t od = take(dmax);
+        if (assign) h->dscr = h->ws + od;
     }
     return off;
 }
@@ -1271,6 +1281,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             else if (opt->smoother == MG_WIREFRAME) orient = LAYOUT_WIREFRAME;
             else if (opt->smoother == MG_ZEBRA_Y) orient = LAYOUT_COLUMNS;
         }
+        if (dim == 3 && !row_only && opt->smoother == MG_TWEED) orient = LAYOUT_TWEED3;
     }
     while (true) {
         Level &L = h->lev[nl];
@@ -1288,12 +1299,15 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         // split layout for the large 2D levels of line smoothers (lines along y
         // contiguous); small levels stay row-major (the coarse-level kernel
         // keeps them in LDS in that layout)
-        L.d.layout = (L.d.nn >= SPLIT_MIN_NODES) ? orient : LAYOUT_ROW;
-        L.d.bs = L.d.layout == LAYOUT_ROW ? L.d.nn : 2 * L.d.nn;
+        // (3D tweed: three planes, one per line axis, from 65^3 nodes on)
+        L.d.layout = (L.d.nn >= (dim == 3 ? SPLIT3_MIN_NODES : SPLIT_MIN_NODES)) ? orient : LAYOUT_ROW;
+        L.d.bs = L.d.layout == LAYOUT_ROW ? L.d.nn : (L.d.layout == LAYOUT_TWEED3 ? 3 : 2) * L.d.nn;
         // the kernels address a problem's array with 32-bit slots (the batch
         // offset is 64-bit): one problem's array must stay below 2^31 entries
         if (L.d.bs > (long long)INT32_MAX) return MG_EUNSUPPORTED;
-        L.g.layout = L.d.layout;
+        // the 3D sweeps address every point of a chunk individually (general
+        // form), so their chunks need no cuts at the planes' borders
+        L.g.layout = L.d.layout == LAYOUT_TWEED3 ? LAYOUT_ROW : L.d.layout;
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
         for (int a = 0; a < dim; ++a) {
@@ -1570,7 +1584,7 @@ template <typename T> int cycle(mg_handle *h, int lv, T *u, const T *f, int adj)
         if ((rc = relax<T>(h, lv, u, f, adj))) return rc;
     Level &C = h->lev[lv + 1];
     T *uc = lev_u<T>(C), *fc = lev_f<T>(C);
-    HIPCHK(launch_residual_restrict<T>(L.d, C.d, coefs<T>(L, adj), u, f, fc, uc, B, h->stream));
+    HIPCHK(launch_residual_restrict<T>(L.d, C.d, coefs<T>(L, adj), u, f, fc, uc, B, h->stream, (T *)h->dscr));
     for (int g = 0; g < h->opt.gamma; ++g)
         if ((rc = cycle<T>(h, lv + 1, uc, fc, adj))) return rc;
     HIPCHK(launch_prolong_add<T>(L.d, C.d, uc, u, B, h->stream));
@@ -1956,7 +1970,8 @@ int mg_residual_restrict(mg_handle *h, int lv, const double *u, const double *f,
         fcc = C.f;
         ucc = C.u;
     }
-    HIPCHK(launch_residual_restrict<double>(L.d, C.d, L.c64[adjoint ? 1 : 0], uu, ff, fcc, ucc, B, h->stream));
+    HIPCHK(launch_residual_restrict<double>(L.d, C.d, L.c64[adjoint ? 1 : 0], uu, ff, fcc, ucc, B, h->stream,
+                                            (double *)h->dscr));
     if (split(C)) {
         HIPCHK(launch_convert<double>(C.d, C.f, fc, 0, B, h->stream));
         HIPCHK(launch_convert<double>(C.d, C.u, uc, 0, B, h->stream));

@@ -118,10 +118,18 @@ struct WGDesc {
 //   LAYOUT_TWEED     : plane C iff i' > j'  (tweed legs along y)
 //   LAYOUT_WIREFRAME : plane C iff i' < j'  (wireframe sides along y)
 //   LAYOUT_COLUMNS   : plane C for every node (lines along y everywhere)
-enum Layout : int { LAYOUT_ROW = 0, LAYOUT_TWEED = 1, LAYOUT_WIREFRAME = 2, LAYOUT_COLUMNS = 3 };
+// LAYOUT_TWEED3 (3D tweed): three planes of nn slots.  A node is kept in the
+// plane of the axis its tweed line runs along, the axis of the smallest of
+// i', j', l' (ties to the lower axis; boundary nodes alike), and each plane
+// stores that axis fastest:
+//   plane 0: i + (nx+1)(j + (ny+1) l)         (x-lines, row-major)
+//   plane 1: nn + j + (ny+1)(i + (nx+1) l)    (y-lines)
+//   plane 2: 2 nn + l + (nz+1)(i + (nx+1) j)  (z-lines)
+enum Layout : int { LAYOUT_ROW = 0, LAYOUT_TWEED = 1, LAYOUT_WIREFRAME = 2, LAYOUT_COLUMNS = 3, LAYOUT_TWEED3 = 4 };
 
 // levels with at least this many nodes use the split layout of their smoother
 constexpr long long SPLIT_MIN_NODES = 129 * 129;
+constexpr long long SPLIT3_MIN_NODES = 65LL * 65 * 65;
 
 struct Dims {
     int dim;
@@ -129,7 +137,7 @@ struct Dims {
     long long st[3];   // row-major node strides: 1, nx+1, (nx+1)(ny+1)
     long long nn;      // nodes per problem
     int layout;        // Layout
-    long long bs;      // array length per problem (batch stride): nn, or 2 nn when split
+    long long bs;      // array length per problem (batch stride): nn, 2 nn (2D split), 3 nn (3D split)
 };
 
 // split layouts: is node (i, j) stored in plane C?
@@ -139,10 +147,29 @@ __host__ __device__ inline bool col_plane(const Dims &d, int i, int j)
     return d.layout == LAYOUT_TWEED ? ip > jp : (d.layout == LAYOUT_WIREFRAME ? ip < jp : true);
 }
 
+// 3D tweed split layout: the plane (axis) of node (i, j, l)
+__host__ __device__ inline int plane3(const Dims &d, int i, int j, int l)
+{
+    const int ip = i < d.n[0] - i ? i : d.n[0] - i, jp = j < d.n[1] - j ? j : d.n[1] - j,
+              lp = l < d.n[2] - l ? l : d.n[2] - l;
+    if (ip <= jp && ip <= lp) return 0;
+    return jp <= lp ? 1 : 2;
+}
+
+// slot of node (i, j, l) in plane pl of the 3D tweed split layout
+__host__ __device__ inline long long plane3_slot(const Dims &d, int pl, int i, int j, int l)
+{
+    const long long S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1;
+    if (pl == 0) return i + S0 * (j + S1 * l);
+    if (pl == 1) return d.nn + j + S1 * (i + S0 * l);
+    return 2 * d.nn + l + S2 * (i + S0 * j);
+}
+
 // slot of node (i, j, l) in an array of layout d.layout
 __host__ __device__ inline long long nidx(const Dims &d, int i, int j, int l)
 {
     if (d.layout == LAYOUT_ROW) return i + j * d.st[1] + l * d.st[2];
+    if (d.layout == LAYOUT_TWEED3) return plane3_slot(d, plane3(d, i, j, l), i, j, l);
     return col_plane(d, i, j) ? d.nn + j + (long long)i * (d.n[1] + 1) : i + j * d.st[1];
 }
 
@@ -268,8 +295,10 @@ hipError_t launch_residual(const Dims &d, const Dims &dout, const Coef<T> &c, co
 template <typename T>
 hipError_t launch_convert(const Dims &d, const T *src, T *dst, int to_split, int batch, hipStream_t s);
 template <typename T>
+// dscr: scratch of one fine-level array (layout fd, batch included) for the
+// 3D split layout, whose restriction runs in two passes (defect, weighting)
 hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T> &c, const T *u, const T *f, T *fc,
-                                    T *uc, int batch, hipStream_t s);
+                                    T *uc, int batch, hipStream_t s, T *dscr = nullptr);
 template <typename T>
 hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u, int batch, hipStream_t s);
 template <typename T>

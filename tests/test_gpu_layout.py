@@ -36,7 +36,9 @@ CASES = [([512, 512], "tanh_wall", 3.0, "tweed", {}),
          ([512, 512], "sinh_centre", 4.0, "wireframe", {"gamma": 2}),
          ([256, 384], "sinh_centre", 3.0, "wireframe", {}),
          ([512, 256], "tanh_wall", 2.0, "zebra_y", {}),
-         ([256, 256], "tanh_wall", 3.0, "tweed", {"batch": 3})]
+         ([256, 256], "tanh_wall", 3.0, "tweed", {"batch": 3}),
+         ([64, 64, 64], "tanh_wall", 2.5, "tweed", {}),
+         ([128, 64, 96], "sinh_centre", 2.0, "tweed", {"batch": 2})]
 
 
 @pytest.mark.parametrize("n,kind,c,sm,kw", CASES)
@@ -105,7 +107,8 @@ def test_split_layout_transfer_operators():
                                                ([256, 256], "sinh_centre", 4.0, "wireframe", 1),
                                                ([256, 128], "tanh_wall", 2.0, "zebra_y", 1),
                                                ([128, 128], "tanh_wall", 2.0, "adz", 2),
-                                               ([64, 64], "tanh_wall", 2.0, "alt_tw", 2)])
+                                               ([64, 64], "tanh_wall", 2.0, "alt_tw", 2),
+                                               ([64, 64, 64], "tanh_wall", 2.5, "tweed", 1)])
 def test_half_sweeps_in_device_layout(n, kind, c, sm, slots):
     """Half-sweeps on device-layout arrays, in the smoother's order, give what
     mg_smooth gives; the layout conversions are exact inverses."""

@@ -94,7 +94,8 @@ SMOOTH_CASES = [([64, 64], "tanh_wall", 3.0, "tweed"), ([96, 96], "tanh_wall", 2
                 ([16, 16, 16], "tanh_wall", 2.5, "tweed"), ([32, 32, 32], "tanh_wall", 2.5, "tweed"),
                 ([24, 16, 32], "tanh_wall", 2.0, "tweed"), ([16, 16, 16], "tanh_wall", 2.5, "zebra_z"),
                 ([16, 16, 16], "tanh_wall", 2.5, "checkerboard"), ([32, 32, 32], "tanh_wall", 2.5, "adz"),
-                ([24, 16, 32], "sinh_centre", 3.0, "adz")]
+                ([24, 16, 32], "sinh_centre", 3.0, "adz"), ([64, 64, 64], "tanh_wall", 2.5, "tweed"),
+                ([96, 64, 80], "sinh_centre", 2.0, "tweed")]
 
 
 @pytest.mark.parametrize("n,kind,c,sm", SMOOTH_CASES)
@@ -119,7 +120,10 @@ def test_smoother(n, kind, c, sm):
                                                ([64, 64], "tanh_wall", 3.0, "checkerboard", 1),
                                                ([64, 64], "tanh_wall", 3.0, "adz", 1),
                                                ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1),
-                                               ([32, 32, 32], "tanh_wall", 2.5, "adz", 1)])
+                                               ([32, 32, 32], "tanh_wall", 2.5, "adz", 1),
+                                               ([64, 64, 64], "tanh_wall", 2.5, "tweed", 1),
+                                               ([96, 64, 80], "sinh_centre", 2.0, "tweed", 1),
+                                               ([48, 80, 72], "tanh_wall", 2.0, "tweed", 1)])
 def test_vcycle(n, kind, c, sm, gamma):
     s = solver(n, kind, c, sm, gamma=gamma)
     H = ohier(n, kind, c, sm)
@@ -142,7 +146,10 @@ def test_vcycle(n, kind, c, sm, gamma):
     ([256, 256], "sinh_centre", 4.0, "wireframe", 2, 1002, "normal"),
     ([128, 96], "tanh_wall", 2.5, "tweed", 1, 1004, "normal"),
     ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1, 1003, "uniform"),
-    ([32, 32, 32], "tanh_wall", 2.5, "adz", 1, 1003, "uniform")])
+    ([32, 32, 32], "tanh_wall", 2.5, "adz", 1, 1003, "uniform"),
+    ([64, 64, 64], "tanh_wall", 2.5, "tweed", 1, 1003, "uniform"),
+    ([96, 64, 80], "tanh_wall", 2.0, "tweed", 1, 1003, "uniform"),
+    ([48, 80, 72], "tanh_wall", 2.0, "tweed", 1, 1003, "uniform")])
 def test_solve_same_cycles(n, kind, c, sm, gamma, seed, dist):
     """mg_solve from u = 0 to 1e-10: same cycle count as the oracle and the
     iterates agree to 1e-12."""

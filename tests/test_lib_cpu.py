@@ -137,10 +137,13 @@ def test_kernel_steps_on_host_match_oracle(n, kind, c, sm):
 @pytest.mark.parametrize("n,kind,c,sm", [([256, 256], "tanh_wall", 3.0, "tweed"), ([256, 128], "tanh_wall", 2.5, "tweed"),
                                         ([256, 256], "sinh_centre", 4.0, "wireframe"),
                                         ([128, 256], "sinh_centre", 3.0, "wireframe"),
-                                        ([256, 192], "tanh_wall", 2.0, "zebra_y"), ([256, 256], "tanh_wall", 2.0, "adz")])
+                                        ([256, 192], "tanh_wall", 2.0, "zebra_y"), ([256, 256], "tanh_wall", 2.0, "adz"),
+                                        ([64, 64, 64], "tanh_wall", 2.5, "tweed"),
+                                        ([80, 64, 72], "sinh_centre", 2.0, "tweed")])
 def test_kernel_steps_in_device_layout_match_oracle(n, kind, c, sm):
     """The same per-lane steps addressing the level's device layout (lines
-    along y stored column-major on the large levels) equal the oracle's sweep."""
+    along y stored column-major on the large 2D levels; in 3D from 65^3 nodes
+    on, three planes with each line axis fastest) equal the oracle's sweep."""
     rc, h = host_handle(n, kind, c, sm)
     assert rc == 0
     xs = [O.coords(kind, c, k) for k in n]
