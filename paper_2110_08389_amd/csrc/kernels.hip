@@ -509,10 +509,18 @@ __device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int c
 // chunk's coefficients itself.
 // C: the chunk capacity (CH, or fewer for the small levels' short chunks;
 // records path only).
+template <int DIM> struct RecOf {
+    using type = ChunkAddr;
+};
+template <> struct RecOf<3> {
+    using type = ChunkAddr3;
+};
+
 template <typename T, int DIM, int NT, bool DOFF, bool REC, int C = CH>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
                                          const T *__restrict__ fb, const Chunk *__restrict__ chunks,
-                                         const ChunkAddr *__restrict__ addrs, const T *__restrict__ cross,
+                                         const typename RecOf<DIM>::type *__restrict__ addrs,
+                                         const T *__restrict__ cross,
                                          const Block *__restrict__ blocks, const WGDesc w,
                                          const NodeFac<T> *__restrict__ fac, int rings)
 {
@@ -524,8 +532,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
     // chunk descriptors (general) or addressing records and along-axis start
     // coordinates (REC)
     __shared__ Chunk s_ch[REC ? 1 : NT];
-    __shared__ ChunkAddr s_ca[REC ? NT : 1];
-    __shared__ int s_cx[REC ? NT : 1];
+    __shared__ typename RecOf<DIM>::type s_ca[REC ? NT : 1];
     __shared__ T s_rs[NT], s_rn[NT], s_dl[NT], s_x[NT];
     __shared__ T s_a[NT / 64], s_b[NT / 64];
     const RedArrays<T> red{nullptr, nullptr, s_rs, nullptr, nullptr, s_rn, s_x, nullptr};
@@ -536,11 +543,16 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         chl = chunks[w.chunk0 + t];
         if (REC) {
             // the record, and the chunk's cross coefficients (constant along
-            // it) in s_rs / s_rn until phase 1 reuses them
+            // it) in s_rs / s_rn (3D: also s_dl / s_x) until phase 1 and the
+            // reduced solve reuse them
             s_ca[t] = addrs[w.chunk0 + t];
-            s_cx[t] = (chl.axdir >> 1) ? chl.c0[1] : chl.c0[0];
-            s_rs[t] = cross[2 * (w.chunk0 + t)];
-            s_rn[t] = cross[2 * (w.chunk0 + t) + 1];
+            constexpr int NCC = DIM == 2 ? 2 : 4;
+            s_rs[t] = cross[NCC * (w.chunk0 + t)];
+            s_rn[t] = cross[NCC * (w.chunk0 + t) + 1];
+            if (DIM == 3) {
+                s_dl[t] = cross[NCC * (w.chunk0 + t) + 2];
+                s_x[t] = cross[NCC * (w.chunk0 + t) + 3];
+            }
         } else {
             s_ch[t] = chl;
         }
@@ -572,36 +584,70 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
         // each issuing all its loads before storing.
         const int lane = t & 63, c0w = t & ~63;
         constexpr int GB = C < 8 ? C : 8;
-        if (c0w < w.nchunk) {
+        if constexpr (DIM == 2) {
+            if (c0w < w.nchunk) {
 #pragma unroll
-            for (int m0 = 0; m0 < C; m0 += GB) {
-                // all of a batch's loads are issued before any is used
-                T fv[GB], um[GB], upv[GB], cm[GB], cp[GB];
-                bool skm[GB], skp[GB];
-                int dst[GB];
+                for (int m0 = 0; m0 < C; m0 += GB) {
+                    // all of a batch's loads are issued before any is used
+                    T fv[GB], um[GB], upv[GB], cm[GB], cp[GB];
+                    bool skm[GB], skp[GB];
+                    int dst[GB];
 #pragma unroll
-                for (int m = 0; m < GB; ++m) {
-                    const int c = c0w + CPS * (m0 + m) + lane / C, k = lane % C;
-                    const bool inc = c < w.nchunk;
-                    const int cc = inc ? c : c0w;
-                    const ChunkAddr a = s_ca[cc];
-                    const bool valid = inc && k < (int)(a.meta & 31);
-                    const RecSlots q = rec_point_slots(d, a, valid ? k : 0);
-                    fv[m] = fb[q.p];
-                    um[m] = ub[q.pm];
-                    upv[m] = ub[q.pp];
-                    skm[m] = q.skm;
-                    skp[m] = q.skp;
-                    cm[m] = s_rs[cc];
-                    cp[m] = s_rn[cc];
-                    dst[m] = inc ? c * PS + k : NT * PS;
+                    for (int m = 0; m < GB; ++m) {
+                        const int c = c0w + CPS * (m0 + m) + lane / C, k = lane % C;
+                        const bool inc = c < w.nchunk;
+                        const int cc = inc ? c : c0w;
+                        const ChunkAddr a = s_ca[cc];
+                        const bool valid = inc && k < (int)(a.meta & 31);
+                        const RecSlots q = rec_point_slots(d, a, valid ? k : 0);
+                        fv[m] = fb[q.p];
+                        um[m] = ub[q.pm];
+                        upv[m] = ub[q.pp];
+                        skm[m] = q.skm;
+                        skp[m] = q.skp;
+                        cm[m] = s_rs[cc];
+                        cp[m] = s_rn[cc];
+                        dst[m] = inc ? c * PS + k : NT * PS;
+                    }
+                    // keep the scheduler from starting the arithmetic (and its
+                    // waits) before the batch's last load has issued
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int m = 0; m < GB; ++m)
+                        s_pt[dst[m]] = rec_rhs_combine<T>(fv[m], um[m], upv[m], cm[m], cp[m], skm[m], skp[m]);
                 }
-                // keep the scheduler from starting the arithmetic (and its
-                // waits) before the batch's last load has issued
-                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            // 3D: f and four cross neighbours per point; the chunk's four
+            // cross coefficients are read from LDS after the batch's loads
+            if (c0w < w.nchunk) {
 #pragma unroll
-                for (int m = 0; m < GB; ++m)
-                    s_pt[dst[m]] = rec_rhs_combine<T>(fv[m], um[m], upv[m], cm[m], cp[m], skm[m], skp[m]);
+                for (int m0 = 0; m0 < C; m0 += GB) {
+                    T fv[GB], uv[GB][4];
+                    unsigned skip[GB];
+                    int dst[GB], ccx[GB];
+#pragma unroll
+                    for (int m = 0; m < GB; ++m) {
+                        const int c = c0w + CPS * (m0 + m) + lane / C, k = lane % C;
+                        const bool inc = c < w.nchunk;
+                        const int cc = inc ? c : c0w;
+                        const ChunkAddr3 a = s_ca[cc];
+                        const bool valid = inc && k < (int)(a.meta & 31);
+                        const Rec3Slots q = rec3_point_slots(d, a, valid ? k : 0);
+                        fv[m] = fb[q.p];
+#pragma unroll
+                        for (int dd = 0; dd < 4; ++dd) uv[m][dd] = ub[q.nb[dd]];
+                        skip[m] = q.skip;
+                        ccx[m] = cc;
+                        dst[m] = inc ? c * PS + k : NT * PS;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int m = 0; m < GB; ++m) {
+                        const T cc4[4] = {s_rs[ccx[m]], s_rn[ccx[m]], s_dl[ccx[m]], s_x[ccx[m]]};
+                        s_pt[dst[m]] = rec3_rhs_combine<T>(fv[m], uv[m], cc4, skip[m]);
+                    }
+                }
             }
         }
         if (t < w.nblock) bkl = blocks[w.block0 + t];
@@ -615,7 +661,8 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             // the chunk's along-axis coefficients (as aligned pairs), its
             // neighbours outside it along its axis and its scalar coefficients
             const int ad = chl.axdir, ax = ad >> 1, up = ad & 1, L = chl.len;
-            const int cax = ax ? chl.c0[1] : chl.c0[0], cL_ = cax + (up ? L - 1 : 1 - L);
+            const int cax = ax == 0 ? chl.c0[0] : (ax == 1 ? chl.c0[1] : (DIM == 3 ? chl.c0[2] : 0));
+            const int cL_ = cax + (up ? L - 1 : 1 - L);
             T Av[C], Cv[C], Bv[C], ubk, ufw;
             const T aL = cf.base[(ad ^ 1) * cf.cs + cL_], bLax = cf.base[(6 + ax) * cf.cs + cL_];
             const T cLf = cf.base[ad * cf.cs + cL_];
@@ -691,9 +738,12 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
             const int c = c0w + CPS * m + lane / C, k = lane % C;
             const bool inc = c < w.nchunk;
             const int cc = inc ? c : cfb;
-            const ChunkAddr a = s_ca[cc];
+            const auto a = s_ca[cc];
             ok[m] = inc && k < (int)(a.meta & 31);
-            slot[m] = rec_slot(d, a, ok[m] ? k : 0);
+            if constexpr (DIM == 2)
+                slot[m] = rec_slot(d, a, ok[m] ? k : 0);
+            else
+                slot[m] = rec3_slot(d, a, ok[m] ? k : 0);
             val[m] = s_pt[cc * PS + k];
         }
 #pragma unroll
@@ -718,16 +768,21 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 template <typename T, int DIM, int NT, bool DOFF, int C = CH>
 __global__ void __launch_bounds__(NT, NT <= twmg::NT / 2 ? 3 : 2) k_block_sweep(Dims d, Coef<T> cf, T *__restrict__ u, const T *__restrict__ f,
                                                     const Chunk *__restrict__ chunks,
-                                                    const ChunkAddr *__restrict__ addrs,
+                                                    const typename RecOf<DIM>::type *__restrict__ addrs,
                                                     const T *__restrict__ cross, const Block *__restrict__ blocks,
                                                     const WGDesc *__restrict__ wgs, const NodeFac<T> *__restrict__ fac,
                                                     int rings)
 {
-    constexpr bool REC = DIM == 2 && NT <= twmg::NT / 2;
+    constexpr bool REC = NT <= twmg::NT / 2;
     const long long boff = (long long)blockIdx.y * d.bs;
     sweep_wg<T, DIM, NT, DOFF, REC, C>(d, cf, u + boff, f + boff, chunks, addrs, cross, blocks, wgs[blockIdx.x], fac,
                                        rings);
 }
+
+// the addressing records of a table, by dimension
+template <int DIM> static const typename RecOf<DIM>::type *rec_table(const SweepTable &tab);
+template <> const ChunkAddr *rec_table<2>(const SweepTable &tab) { return tab.addrs; }
+template <> const ChunkAddr3 *rec_table<3>(const SweepTable &tab) { return tab.addrs3; }
 
 template <typename T, int DIM, bool DOFF>
 static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const T *f, const SweepTable &tab,
@@ -735,6 +790,7 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
                                    const SideStream &side)
 {
     const int rings = tab.rings ? 1 : 0;
+    const typename RecOf<DIM>::type *recs = rec_table<DIM>(tab);
     // workgroups holding a block of more than NT/2 chunks come first and run
     // with NT lanes; the rest run with NT/2 lanes (a third of the LDS), so that
     // several workgroups share a CU and hide each other's memory waits.  With
@@ -752,32 +808,32 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
     }
     if (tab.nwg_big > 0)
         hipLaunchKernelGGL((k_block_sweep<T, DIM, NT, DOFF>), dim3(tab.nwg_big, batch), dim3(NT), 0, s, d, c, u, f,
-                           tab.chunks, tab.addrs, cross, tab.blocks, tab.wgs, fac, rings);
+                           tab.chunks, recs, cross, tab.blocks, tab.wgs, fac, rings);
     if (tab.nwg > tab.nwg_big) {
         const dim3 grid(tab.nwg - tab.nwg_big, batch);
         const WGDesc *wsm = tab.wgs + tab.nwg_big;
         if (tab.nts == NT / 2 && tab.cap == CH) {
             hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, ss, d, c, u, f,
-                               tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                               tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
         } else {
             if constexpr (DIM == 2) {
                 // narrow workgroups (2D levels bound by a workgroup's latency),
                 // with chunks of up to 16 or of up to 8 points
                 if (tab.nts == 64 && tab.cap == CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, ss, d, c, u, f,
-                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                                       tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else if (tab.nts == 128 && tab.cap == CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF>), grid, dim3(128), 0, ss, d, c, u, f,
-                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                                       tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else if (tab.nts == 64 && tab.cap == SHORT_CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF, SHORT_CH>), grid, dim3(64), 0, ss, d, c, u, f,
-                                       tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                                       tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else if (tab.nts == 128 && tab.cap == SHORT_CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 128, DOFF, SHORT_CH>), grid, dim3(128), 0, ss, d, c, u,
-                                       f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                                       f, tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else if (tab.nts == NT / 2 && tab.cap == SHORT_CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF, SHORT_CH>), grid, dim3(NT / 2), 0, ss, d, c,
-                                       u, f, tab.chunks, tab.addrs, cross, tab.blocks, wsm, fac, rings);
+                                       u, f, tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else
                     return hipErrorInvalidValue;
             } else {
@@ -1172,14 +1228,18 @@ __device__ __forceinline__ T prolong_at(const Dims &cd, const T *eb, int i, int 
 template <int PL> struct PlaneAxes {
     static constexpr int F = PL, A = PL == 0 ? 1 : 0, B = PL == 2 ? 1 : 2;
 };
-template <int PL> __host__ __device__ __forceinline__ int ptiles(const Dims &d)
+template <int PL> struct PlaneC {
+    static constexpr int value = PL;
+};
+// tiles of plane PL: 16 nodes along F, 4 along A, 4 NB along B
+template <int PL, int NB> __host__ __device__ __forceinline__ int ptiles(const Dims &d)
 {
     using X = PlaneAxes<PL>;
-    return ((d.n[X::F] + 16) / 16) * ((d.n[X::A] + 4) / 4) * ((d.n[X::B] + 4) / 4);
+    return ((d.n[X::F] + 16) / 16) * ((d.n[X::A] + 4) / 4) * ((d.n[X::B] + 4 * NB) / (4 * NB));
 }
-__host__ __device__ __forceinline__ int tiles3(const Dims &d)
+template <int NB> __host__ __device__ __forceinline__ int tiles3(const Dims &d)
 {
-    return d.layout == LAYOUT_TWEED3 ? ptiles<0>(d) + ptiles<1>(d) + ptiles<2>(d) : ptiles<0>(d);
+    return d.layout == LAYOUT_TWEED3 ? ptiles<0, NB>(d) + ptiles<1, NB>(d) + ptiles<2, NB>(d) : ptiles<0, NB>(d);
 }
 template <int PL> __device__ __forceinline__ int slot_in_plane(const Dims &d, int i, int j, int l)
 {
@@ -1188,65 +1248,116 @@ template <int PL> __device__ __forceinline__ int slot_in_plane(const Dims &d, in
     if (PL == 1) return nn + j + S1 * (i + S0 * l);
     return 2 * nn + l + S2 * (i + S0 * j);
 }
+// strides of the A and B axes in plane PL (F has stride 1); the row-major
+// layout is plane 0
+template <int PL> __device__ __forceinline__ int stride_a(const Dims &d)
+{
+    return PL == 0 ? d.n[0] + 1 : (PL == 1 ? d.n[1] + 1 : d.n[2] + 1);
+}
+template <int PL> __device__ __forceinline__ int stride_b(const Dims &d)
+{
+    return (d.n[0] + 1) * (PL == 0 ? d.n[1] + 1 : (PL == 1 ? d.n[1] + 1 : d.n[2] + 1));
+}
+// (i, j, l) of the node at (f, a, b) in plane PL's axes
+template <int PL> __device__ __forceinline__ void plane_xyz(int f, int a, int b, int &i, int &j, int &l)
+{
+    using X = PlaneAxes<PL>;
+    int c[3];
+    c[X::F] = f;
+    c[X::A] = a;
+    c[X::B] = b;
+    i = c[0];
+    j = c[1];
+    l = c[2];
+}
+// how far node (i, j, l), kept in plane PL, lies inside the plane's region
+// (as P3::margin); large for the row-major layout
+template <int PL> __device__ __forceinline__ int margin3(const Dims &d, int i, int j, int l)
+{
+    if (d.layout != LAYOUT_TWEED3) return 1 << 20;
+    const int ip = min(i, d.n[0] - i), jp = min(j, d.n[1] - j), lp = min(l, d.n[2] - l);
+    const int own = PL == 0 ? ip : (PL == 1 ? jp : lp);
+    const int o1 = PL == 0 ? jp : ip, o2 = PL == 2 ? jp : lp;
+    return min(o1, o2) - own;
+}
 
-// Node threadIdx.x of tile t of plane PL: op(i, j, l, slot) when the node is
-// in the grid and kept in plane PL.  A tile whose 8 corners all lie in other
-// planes, and that does not straddle a centre line n/2, is skipped whole:
-// away from the centre lines the primed coordinates are monotone along each
-// axis inside a tile, so the plane's region (an intersection of half-spaces
-// in them) meets the tile only if it holds a corner.
-template <int PL, typename Op>
+// Tile t of plane PL: this thread's column of NB consecutive nodes along B,
+// op(PlaneC<PL>, f, a, b) with the first node's coordinates along F, A, B
+// (b a multiple of NB) unless the whole column lies outside the grid.  A tile
+// whose 8 corners all lie in other planes, and that does not straddle a
+// centre line n/2, is skipped whole: away from the centre lines the primed
+// coordinates are monotone along each axis inside a tile, so the plane's
+// region (an intersection of half-spaces in them) meets the tile only if it
+// holds a corner.
+template <int PL, int NB, typename Op>
 __device__ __forceinline__ void tile3_plane(const Dims &d, int t, Op &&op)
 {
     using X = PlaneAxes<PL>;
+    constexpr int TB = 4 * NB;
     const int tf = (d.n[X::F] + 16) / 16, ta = (d.n[X::A] + 4) / 4;
-    const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * 4;
+    const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * TB;
     if (d.layout == LAYOUT_TWEED3) {
         const int nf = d.n[X::F], na = d.n[X::A], nb = d.n[X::B];
-        const int f1 = min(f0 + 15, nf), a1 = min(a0 + 3, na), b1 = min(b0 + 3, nb);
+        const int f1 = min(f0 + 15, nf), a1 = min(a0 + 3, na), b1 = min(b0 + TB - 1, nb);
         bool any = (f0 < nf / 2 && f1 > nf / 2) || (a0 < na / 2 && a1 > na / 2) || (b0 < nb / 2 && b1 > nb / 2);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            int c[3];
-            c[X::F] = (k & 1) ? f1 : f0;
-            c[X::A] = (k & 2) ? a1 : a0;
-            c[X::B] = (k & 4) ? b1 : b0;
-            any = any || plane3(d, c[0], c[1], c[2]) == PL;
+            int i, j, l;
+            plane_xyz<PL>((k & 1) ? f1 : f0, (k & 2) ? a1 : a0, (k & 4) ? b1 : b0, i, j, l);
+            any = any || plane3(d, i, j, l) == PL;
         }
         if (!any) return;
     }
     const int q = threadIdx.x;
-    int c[3];
-    c[X::F] = f0 + (q & 15);
-    c[X::A] = a0 + ((q >> 4) & 3);
-    c[X::B] = b0 + (q >> 6);
-    if (c[0] > d.n[0] || c[1] > d.n[1] || c[2] > d.n[2]) return;
-    if (d.layout == LAYOUT_TWEED3 && plane3(d, c[0], c[1], c[2]) != PL) return;
-    op(c[0], c[1], c[2], slot_in_plane<PL>(d, c[0], c[1], c[2]));
+    const int f = f0 + (q & 15), a = a0 + ((q >> 4) & 3), b = b0 + NB * (q >> 6);
+    if (f > d.n[X::F] || a > d.n[X::A] || b > d.n[X::B]) return;
+    op(PlaneC<PL>(), f, a, b);
 }
 
 // 3D stencil kernels walk the nodes of every plane of the layout in tiles of
-// 16 along the plane's fast axis by 4 x 4 across it (256 nodes, one per
-// thread: a wavefront reads four whole 128-byte runs).  A tile handles only
-// the nodes kept in its plane, so the three tile families visit every node
-// once; the row-major layout has plane 0 only.  The plane is uniform per
-// workgroup and a template argument below the branch, so no coordinate is
-// picked by a run-time axis index.
-template <typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int t, Op &&op)
+// 16 along the plane's fast axis F by 4 along A by 4 NB along B, a thread
+// holding NB consecutive nodes along B (a wavefront reads four whole 128-byte
+// runs per load): the loads of a column are issued together and the values
+// its nodes share (neighbours along B, coefficients along F and A, coarse
+// values) are read once.  A tile handles only the nodes kept in its plane, so
+// the three tile families visit every node once; the row-major layout has
+// plane 0 only.  The plane is uniform per workgroup and a template argument
+// below the branch, so no coordinate is picked by a run-time axis index.
+template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int t, Op &&op)
 {
-    const int t0 = ptiles<0>(d);
+    const int t0 = ptiles<0, NB>(d);
     if (t < t0) {
-        tile3_plane<0>(d, t, op);
+        tile3_plane<0, NB>(d, t, op);
         return;
     }
     t -= t0;
-    const int t1 = ptiles<1>(d);
+    const int t1 = ptiles<1, NB>(d);
     if (t < t1)
-        tile3_plane<1>(d, t, op);
+        tile3_plane<1, NB>(d, t, op);
     else
-        tile3_plane<2>(d, t - t1, op);
+        tile3_plane<2, NB>(d, t - t1, op);
 }
 __device__ __forceinline__ int tile3_index(int it, int nt) { return (int)gridDim.x == nt ? xcd_tile(it, nt) : it; }
+
+// The NB nodes of a column: coordinates, slots in plane PL, ok (in the grid
+// and kept in plane PL) and in (also interior)
+template <int NB> struct Col3 {
+    int i[NB], j[NB], l[NB], sl[NB];
+    bool ok[NB], in[NB];
+};
+template <int PL, int NB> __device__ __forceinline__ Col3<NB> col3(const Dims &d, int f, int a, int b)
+{
+    using X = PlaneAxes<PL>;
+    Col3<NB> c;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        plane_xyz<PL>(f, a, b + k, c.i[k], c.j[k], c.l[k]);
+        c.ok[k] = b + k <= d.n[X::B] && (d.layout != LAYOUT_TWEED3 || plane3(d, c.i[k], c.j[k], c.l[k]) == PL);
+        c.in[k] = c.ok[k] && interior<3>(d, c.i[k], c.j[k], c.l[k]);
+        c.sl[k] = slot_in_plane<PL>(d, c.i[k], c.j[k], c.l[k]);
+    }
+    return c;
+}
 
 // 32-bit slot of a 3D node and its plane's strides (every per-problem array
 // is below 2^31 entries, which set-up checks); margin as for P3.  For the
@@ -1358,20 +1469,101 @@ __device__ __forceinline__ void defects3(const Dims &d, const Coef<T> &cf, const
     }
 }
 
+// nodes per thread of the 3D stencil kernels (the restriction reads a 3 x 3
+// box per fine plane of its column, so it holds fewer)
+constexpr int COL_NB = 2, COL_NB_RESTRICT = 2;
+
+// Defects of a column's nodes (0 where not interior).  When every node is
+// interior and has its six neighbours in its plane, the column's values are
+// read at the plane's strides, each neighbour along B once; otherwise every
+// node is addressed in general form.  Same summation order as defect_at.
+template <typename T, int PL, int NB>
+__device__ __forceinline__ void col_defects(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                            const T *__restrict__ fb, const Col3<NB> &c, T (&out)[NB])
+{
+    using X = PlaneAxes<PL>;
+    bool fast = true;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) fast = fast && c.in[k] && margin3<PL>(d, c.i[k], c.j[k], c.l[k]) >= 2;
+    if (fast) {
+        const int sa = stride_a<PL>(d), sb = stride_b<PL>(d), p0 = c.sl[0];
+        int cc[3];
+        cc[0] = c.i[0];
+        cc[1] = c.j[0];
+        cc[2] = c.l[0];
+        const int f = cc[X::F], a = cc[X::A], b = cc[X::B];
+        T ucol[NB + 2], um[NB][2], ua[NB][2], fv[NB], lb[NB], hb[NB], gb[NB];
+#pragma unroll
+        for (int m = 0; m < NB + 2; ++m) ucol[m] = ub[p0 + (m - 1) * sb];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int p = p0 + k * sb;
+            um[k][0] = ub[p - 1];
+            um[k][1] = ub[p + 1];
+            ua[k][0] = ub[p - sa];
+            ua[k][1] = ub[p + sa];
+            fv[k] = fb[p];
+            lb[k] = cf.lo[X::B][b + k];
+            hb[k] = cf.hi[X::B][b + k];
+            gb[k] = cf.dg[X::B][b + k];
+        }
+        const T lf = cf.lo[X::F][f], hf = cf.hi[X::F][f], gf = cf.dg[X::F][f];
+        const T la = cf.lo[X::A][a], ha = cf.hi[X::A][a], ga = cf.dg[X::A][a];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            T lo[3], hi[3], dg[3], vm[3], vp[3];
+            lo[X::F] = lf;
+            hi[X::F] = hf;
+            dg[X::F] = gf;
+            vm[X::F] = um[k][0];
+            vp[X::F] = um[k][1];
+            lo[X::A] = la;
+            hi[X::A] = ha;
+            dg[X::A] = ga;
+            vm[X::A] = ua[k][0];
+            vp[X::A] = ua[k][1];
+            lo[X::B] = lb[k];
+            hi[X::B] = hb[k];
+            dg[X::B] = gb[k];
+            vm[X::B] = ucol[k];
+            vp[X::B] = ucol[k + 2];
+            T sum = lo[0] * vm[0] + hi[0] * vp[0];
+            sum += lo[1] * vm[1] + hi[1] * vp[1];
+            T g = dg[0] + dg[1];
+            sum += lo[2] * vm[2] + hi[2] * vp[2];
+            g += dg[2];
+            out[k] = fv[k] - (sum + g * ucol[k + 1]);
+        }
+    } else {
+        // one node at a time: the general form holds few values in flight
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int i1[1] = {c.i[k]}, j1[1] = {c.j[k]}, l1[1] = {c.l[k]};
+            const bool in1[1] = {c.in[k]};
+            T o1[1];
+            defects3<T, 1>(d, cf, ub, fb, i1, j1, l1, in1, o1);
+            out[k] = o1[0];
+        }
+    }
+}
+
 // defect d = f - L u of every node (0 on boundary nodes) into r (layout of d)
 template <typename T>
 __global__ void __launch_bounds__(256) k_residual3(Dims d, Coef<T> cf, const T *__restrict__ u,
                                                    const T *__restrict__ f, T *__restrict__ r)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3(d);
+    const int nt = tiles3<COL_NB>(d);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int sl) {
-            const int ia[1] = {i}, ja[1] = {j}, la[1] = {l};
-            const bool in[1] = {interior<3>(d, i, j, l)};
-            T dv[1];
-            defects3<T, 1>(d, cf, u + boff, f + boff, ia, ja, la, in, dv);
-            r[boff + sl] = dv[0];
+        tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
+            constexpr int PL = decltype(plc)::value;
+            const Col3<COL_NB> c = col3<PL, COL_NB>(d, fq, aq, bq);
+            T dv[COL_NB];
+            col_defects<T, PL, COL_NB>(d, cf, u + boff, f + boff, c, dv);
+#pragma unroll
+            for (int k = 0; k < COL_NB; ++k)
+                if (c.ok[k]) r[boff + c.sl[k]] = dv[k];
         });
 }
 
@@ -1383,19 +1575,22 @@ __global__ void __launch_bounds__(256) k_resnorm3(Dims d, Coef<T> cf, const T *_
                                                   double *__restrict__ partial)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3(d);
+    const int nt = tiles3<COL_NB>(d);
     double m = 0.0;
     bool nan = false;
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int sl) {
-            const int ia[1] = {i}, ja[1] = {j}, la[1] = {l};
-            const bool in[1] = {interior<3>(d, i, j, l)};
-            T dv[1];
-            defects3<T, 1>(d, cf, u + boff, f + boff, ia, ja, la, in, dv);
-            if (TO32) r32[boff + sl] = (float)dv[0];
-            const double a = fabs((double)dv[0]);
-            nan = nan || (a != a);
-            m = fmax(m, a);
+        tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
+            constexpr int PL = decltype(plc)::value;
+            const Col3<COL_NB> c = col3<PL, COL_NB>(d, fq, aq, bq);
+            T dv[COL_NB];
+            col_defects<T, PL, COL_NB>(d, cf, u + boff, f + boff, c, dv);
+#pragma unroll
+            for (int k = 0; k < COL_NB; ++k) {
+                if (TO32 && c.ok[k]) r32[boff + c.sl[k]] = (float)dv[k];
+                const double av = fabs((double)dv[k]);
+                nan = nan || (av != av);
+                m = fmax(m, av);
+            }
         });
     if (nan) m = __builtin_inf();
     m = block_max(m);
@@ -1426,61 +1621,179 @@ __device__ __forceinline__ T prolong3_at(const Dims &cd, const T *eb, int i, int
     return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
 }
 
+// u += P e_c over a column of fine nodes (b even).  When every node is
+// interior and the coarse box the column interpolates from (2 x 2 across,
+// NB/2 + 1 along B) lies in one coarse plane, the box is read once at that
+// plane's strides; otherwise each node is interpolated as prolong3_at.  Same
+// arithmetic as prolong_at.
+template <typename T, int PL, int NB>
+__device__ __forceinline__ void col_prolong(const Dims &fd, const Dims &cd, const T *__restrict__ eb,
+                                            T *__restrict__ ub, const Col3<NB> &c, int f, int a, int b)
+{
+    using X = PlaneAxes<PL>;
+    constexpr int MB = NB / 2 + 1;
+    bool all_in = true;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) all_in = all_in && c.in[k];
+    int I0, J0, K0;
+    plane_xyz<PL>(f >> 1, a >> 1, b >> 1, I0, J0, K0);
+    const P3i q = p3i_at(cd, I0, J0, K0);
+    if (all_in && q.margin >= 2 * (MB - 1) + 1 && q.margin >= 3) {
+        int st[3];
+        st[0] = q.sx;
+        st[1] = q.sy;
+        st[2] = q.sz;
+        const int sF = st[X::F], sA = st[X::A], sB = st[X::B];
+        T cv[MB][2][2], uv[NB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+                for (int iff = 0; iff < 2; ++iff) cv[m][ia][iff] = eb[q.p + m * sB + ia * sA + iff * sF];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) uv[k] = ub[c.sl[k]];
+        __builtin_amdgcn_sched_barrier(0);
+        // equal end indices (the fine coordinate is even) per x, y, z
+        bool eqF = !(f & 1), eqA = !(a & 1);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            bool eq[3];
+            eq[X::F] = eqF;
+            eq[X::A] = eqA;
+            eq[X::B] = !(k & 1);
+            // coarse value at selectors (sx, sy, sz) in {0, 1}: index 0 is
+            // the lower end, 1 the upper
+            auto cval = [&](int sx, int sy, int sz) -> T {
+                int sel[3];
+                sel[0] = sx;
+                sel[1] = sy;
+                sel[2] = sz;
+                const int mb = sel[X::B] ? (k + 1) >> 1 : k >> 1;
+                return cv[mb][sel[X::A]][sel[X::F]];
+            };
+            T pl2[2];
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const T r0 = eq[0] ? cval(0, 0, kk) : T(0.5) * (cval(0, 0, kk) + cval(1, 0, kk));
+                const T r1 = eq[0] ? cval(0, 1, kk) : T(0.5) * (cval(0, 1, kk) + cval(1, 1, kk));
+                pl2[kk] = eq[1] ? r0 : T(0.5) * (r0 + r1);
+            }
+            ub[c.sl[k]] = uv[k] + (eq[2] ? pl2[0] : T(0.5) * (pl2[0] + pl2[1]));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (c.in[k]) ub[c.sl[k]] += prolong3_at<T>(cd, eb, c.i[k], c.j[k], c.l[k]);
+    }
+}
+
 // u += P e_c at fine interior nodes
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong3(Dims fd, Dims cd, const T *__restrict__ ec, T *__restrict__ u)
 {
     T *ub = u + (long long)blockIdx.y * fd.bs;
     const T *eb = ec + (long long)blockIdx.y * cd.bs;
-    const int nt = tiles3(fd);
+    const int nt = tiles3<COL_NB>(fd);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit(fd, tile3_index(it, nt), [&](int i, int j, int l, int p) {
-            if (interior<3>(fd, i, j, l)) ub[p] += prolong3_at<T>(cd, eb, i, j, l);
+        tile3_visit<COL_NB>(fd, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
+            constexpr int PL = decltype(plc)::value;
+            const Col3<COL_NB> c = col3<PL, COL_NB>(fd, fq, aq, bq);
+            col_prolong<T, PL, COL_NB>(fd, cd, eb, ub, c, fq, aq, bq);
         });
 }
 
 // full weighting of the defect array dr (fine layout, 0 on boundary nodes)
 // at coarse interior nodes, over coarse tiles; clears the coarse correction.
-// Same weights and summation order as restrict_at.
+// A column of coarse nodes reads the fine 3 x 3 boxes of its 2 NB + 1 fine
+// planes along B once when every node's fine 3 x 3 x 3 box lies 3 or more
+// inside one fine plane (then all of them lie in the same one); otherwise
+// each node is addressed in general form.  Same weights and summation order
+// as restrict_at.
+template <typename T, int PL, int NB>
+__device__ __forceinline__ void col_restrict(const Dims &fd, const Dims &cd, const T *__restrict__ db,
+                                             T *__restrict__ fcb, T *__restrict__ ucb, const Col3<NB> &c)
+{
+    using X = PlaneAxes<PL>;
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+    bool fast = true;
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        fast = fast && c.in[k] && p3i_at(fd, 2 * c.i[k], 2 * c.j[k], 2 * c.l[k]).margin >= 3;
+    if (fast) {
+        const P3i pc = p3i_at(fd, 2 * c.i[0], 2 * c.j[0], 2 * c.l[0]);
+        int st[3];
+        st[0] = pc.sx;
+        st[1] = pc.sy;
+        st[2] = pc.sz;
+        const int sF = st[X::F], sA = st[X::A], sB = st[X::B];
+        // fine planes m = 0 .. 2 NB along B from the first node's centre - 1
+        T v[2 * NB + 1][3][3];
+#pragma unroll
+        for (int m = 0; m < 2 * NB + 1; ++m)
+#pragma unroll
+            for (int oa = 0; oa < 3; ++oa)
+#pragma unroll
+                for (int of = 0; of < 3; ++of) v[m][oa][of] = db[pc.p + (m - 1) * sB + (oa - 1) * sA + (of - 1) * sF];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            T acc = 0;
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy) {
+                    T rowacc = 0;
+#pragma unroll
+                    for (int cx = -1; cx <= 1; ++cx) {
+                        int o[3];
+                        o[0] = cx;
+                        o[1] = cy;
+                        o[2] = cz;
+                        rowacc += w3[cx + 1] * v[2 * k + 1 + o[X::B]][o[X::A] + 1][o[X::F] + 1];
+                    }
+                    acc += w3[cz + 1] * w3[cy + 1] * rowacc;
+                }
+            }
+            fcb[c.sl[k]] = acc;
+            ucb[c.sl[k]] = T(0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (!c.in[k]) continue;
+            const int I = c.i[k], J = c.j[k], K = c.l[k];
+            T acc = 0;
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy) {
+                    T rowacc = 0;
+#pragma unroll
+                    for (int cx = -1; cx <= 1; ++cx)
+                        rowacc += w3[cx + 1] * db[slot3(fd, 2 * I + cx, 2 * J + cy, 2 * K + cz)];
+                    acc += w3[cz + 1] * w3[cy + 1] * rowacc;
+                }
+            }
+            fcb[c.sl[k]] = acc;
+            ucb[c.sl[k]] = T(0);
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fw_restrict3(Dims fd, Dims cd, const T *__restrict__ dr, T *__restrict__ fc,
                                                       T *__restrict__ uc)
 {
     const T *db = dr + (long long)blockIdx.y * fd.bs;
     const long long cboff = (long long)blockIdx.y * cd.bs;
-    const int nt = tiles3(cd);
+    constexpr int NB = COL_NB_RESTRICT;
+    const int nt = tiles3<NB>(cd);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit(cd, tile3_index(it, nt), [&](int I, int J, int K, int pcs) {
-            if (!interior<3>(cd, I, J, K)) return;
-            // the fine 3 x 3 x 3 box at fixed offsets in the plane of its
-            // centre when that centre lies 3 or more inside it
-            const P3i pc = p3i_at(fd, 2 * I, 2 * J, 2 * K);
-            const bool fast = pc.margin >= 3;
-            T v[27];
-#pragma unroll
-            for (int cz = -1; cz <= 1; ++cz)
-#pragma unroll
-                for (int b = -1; b <= 1; ++b)
-#pragma unroll
-                    for (int a = -1; a <= 1; ++a)
-                        v[(cz + 1) * 9 + (b + 1) * 3 + (a + 1)] =
-                            db[fast ? pc.p + a * pc.sx + b * pc.sy + cz * pc.sz
-                                    : slot3(fd, 2 * I + a, 2 * J + b, 2 * K + cz)];
-            __builtin_amdgcn_sched_barrier(0);
-            const T w3[3] = {T(0.25), T(0.5), T(0.25)};
-            T acc = 0;
-#pragma unroll
-            for (int cz = -1; cz <= 1; ++cz) {
-#pragma unroll
-                for (int b = -1; b <= 1; ++b) {
-                    T rowacc = 0;
-#pragma unroll
-                    for (int a = -1; a <= 1; ++a) rowacc += w3[a + 1] * v[(cz + 1) * 9 + (b + 1) * 3 + (a + 1)];
-                    acc += w3[cz + 1] * w3[b + 1] * rowacc;
-                }
-            }
-            fc[cboff + pcs] = acc;
-            uc[cboff + pcs] = T(0);
+        tile3_visit<NB>(cd, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
+            constexpr int PL = decltype(plc)::value;
+            const Col3<NB> c = col3<PL, NB>(cd, fq, aq, bq);
+            col_restrict<T, PL, NB>(fd, cd, db, fc + cboff, uc + cboff, c);
         });
 }
 
@@ -1488,17 +1801,29 @@ __global__ void __launch_bounds__(256) k_fw_restrict3(Dims fd, Dims cd, const T 
 __global__ void __launch_bounds__(256) k_ir_update3(Dims d, double *__restrict__ u, const float *__restrict__ e)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3(d);
+    const int nt = tiles3<COL_NB>(d);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit(d, tile3_index(it, nt), [&](int i, int j, int l, int p) {
-            if (interior<3>(d, i, j, l)) u[boff + p] += (double)e[boff + p];
+        tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
+            constexpr int PL = decltype(plc)::value;
+            const Col3<COL_NB> c = col3<PL, COL_NB>(d, fq, aq, bq);
+            double uv[COL_NB];
+            float ev[COL_NB];
+#pragma unroll
+            for (int k = 0; k < COL_NB; ++k) {
+                const long long p = boff + (c.in[k] ? c.sl[k] : c.sl[0]);
+                uv[k] = u[p];
+                ev[k] = e[p];
+            }
+#pragma unroll
+            for (int k = 0; k < COL_NB; ++k)
+                if (c.in[k]) u[boff + c.sl[k]] = uv[k] + (double)ev[k];
         });
 }
 
 // workgroups of a 3D tile launch: one per tile up to 65535
-static int tile3_grid(const Dims &d)
+template <int NB> static int tile3_grid(const Dims &d)
 {
-    const int nt = tiles3(d);
+    const int nt = tiles3<NB>(d);
     return nt < 65535 ? nt : 65535;
 }
 
@@ -1515,8 +1840,8 @@ hipError_t launch_residual_restrict(const Dims &fd, const Dims &cd, const Coef<T
         // each fine defect once, into the scratch array (fine layout), then
         // the 27-point weighting from it
         if (!dscr) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_residual3<T>), dim3(tile3_grid(fd), batch), dim3(256), 0, s, fd, c, u, f, dscr);
-        hipLaunchKernelGGL((k_fw_restrict3<T>), dim3(tile3_grid(cd), batch), dim3(256), 0, s, fd, cd, dscr, fc, uc);
+        hipLaunchKernelGGL((k_residual3<T>), dim3(tile3_grid<COL_NB>(fd), batch), dim3(256), 0, s, fd, c, u, f, dscr);
+        hipLaunchKernelGGL((k_fw_restrict3<T>), dim3(tile3_grid<COL_NB_RESTRICT>(cd), batch), dim3(256), 0, s, fd, cd, dscr, fc, uc);
         return hipGetLastError();
     }
     dim3 grid(row_grid(cd), batch);
@@ -1536,7 +1861,7 @@ hipError_t launch_prolong_add(const Dims &fd, const Dims &cd, const T *ec, T *u,
         hipLaunchKernelGGL((k_prolong_tile<T>), tiles, dim3(256), 0, s, fd, cd, ec, u);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_prolong3<T>), dim3(tile3_grid(fd), batch), dim3(256), 0, s, fd, cd, ec, u);
+    hipLaunchKernelGGL((k_prolong3<T>), dim3(tile3_grid<COL_NB>(fd), batch), dim3(256), 0, s, fd, cd, ec, u);
     return hipGetLastError();
 }
 
@@ -1918,7 +2243,7 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
         if (gx > nt) gx = nt;
         hipLaunchKernelGGL((k_resnorm_tile<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     } else {
-        if (gx > tiles3(d)) gx = tiles3(d);
+        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
         hipLaunchKernelGGL((k_resnorm3<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
@@ -1938,7 +2263,7 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
         hipLaunchKernelGGL((k_resnorm_tile<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32,
                            partial);
     } else {
-        if (gx > tiles3(d)) gx = tiles3(d);
+        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
         hipLaunchKernelGGL((k_resnorm3<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
@@ -1996,7 +2321,7 @@ hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const do
         hipLaunchKernelGGL((k_resnorm_tile<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     } else {
-        if (gx > tiles3(d)) gx = tiles3(d);
+        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
         hipLaunchKernelGGL((k_resnorm3<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     }
@@ -2025,7 +2350,7 @@ hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch,
 {
     dim3 grid(row_grid(d), batch);
     if (d.dim == 2) hipLaunchKernelGGL((k_ir_update<2>), grid, dim3(256), 0, s, d, u, e);
-    else hipLaunchKernelGGL(k_ir_update3, dim3(tile3_grid(d), batch), dim3(256), 0, s, d, u, e);
+    else hipLaunchKernelGGL(k_ir_update3, dim3(tile3_grid<COL_NB>(d), batch), dim3(256), 0, s, d, u, e);
     return hipGetLastError();
 }
 

@@ -412,6 +412,135 @@ __host__ __device__ __forceinline__ void chunk_cross_coefs(const Coef<T> &cf, co
     cp = cf.base[(2 * a2 + 1) * cf.cs + cc];
 }
 
+// ---- 3D addressing records -------------------------------------------------
+// the two axes across chunk axis ax, in increasing order
+__host__ __device__ __forceinline__ int cross_axis3(int ax, int q) { return q == 0 ? (ax == 0 ? 1 : 0) : (ax == 2 ? 1 : 2); }
+
+// signed stride between consecutive points of a 3D chunk
+__host__ __device__ __forceinline__ int rec3_step(const Dims &d, uint32_t meta)
+{
+    const int ax = (meta >> 18) & 3, up = (meta >> 20) & 1;
+    const int m = d.layout == LAYOUT_TWEED3 ? 1 : (ax == 0 ? 1 : (ax == 1 ? (int)d.st[1] : (int)d.st[2]));
+    return up ? m : -m;
+}
+
+// Addressing record of a 3D chunk (host, at setup).  Returns false when a
+// point leaves the chunk's run of slots or more than one point has cross
+// neighbours off the regular offsets (the caller rejects the level).
+inline bool make_chunk_addr3(const Dims &d, const Chunk &ch, ChunkAddr3 &a)
+{
+    const int L = ch.len, ad = ch.axdir, ax = ad >> 1;
+    const int sg = (ad & 1) ? 1 : -1;
+    const int e[3] = {ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0};
+    const int q0 = cross_axis3(ax, 0), q1 = cross_axis3(ax, 1);
+    const int c0[3] = {ch.c0[0], ch.c0[1], ch.c0[2]};
+    auto slot_at = [&](int k, int qa, int dq) {
+        int c[3] = {c0[0] + k * e[0], c0[1] + k * e[1], c0[2] + k * e[2]};
+        if (qa >= 0) c[qa] += dq;
+        return slot32(d, c[0], c[1], c[2]);
+    };
+    const int p0 = slot_at(0, -1, 0);
+    // regular cross strides: those of the axes in the chunk's plane
+    const int S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1;
+    const int pl = d.layout == LAYOUT_TWEED3 ? plane3(d, c0[0], c0[1], c0[2]) : 0;
+    const int str[3][3] = {{1, S0, S0 * S1}, {S1, 1, S1 * S0}, {S2, S2 * S0, 1}};
+    const int s0 = str[pl][q0], s1 = str[pl][q1];
+    uint32_t meta = (uint32_t)L | ((uint32_t)ax << 18) | ((uint32_t)(sg > 0) << 20);
+    a.p0 = p0;
+    a.s[0] = s0;
+    a.s[1] = s1;
+    a.irr[0] = a.irr[1] = a.irr[2] = a.irr[3] = 0;
+    const int step = rec3_step(d, meta);
+    int kx = 31;
+    uint32_t xmask = 0;
+    for (int k = 0; k < L; ++k) {
+        const int p = slot_at(k, -1, 0);
+        if (p != p0 + k * step) return false;
+        const int nb[4] = {slot_at(k, q0, -1), slot_at(k, q0, 1), slot_at(k, q1, -1), slot_at(k, q1, 1)};
+        const int rg[4] = {p - s0, p + s0, p - s1, p + s1};
+        for (int dd = 0; dd < 4; ++dd) {
+            if (nb[dd] == rg[dd]) continue;
+            if (kx != 31 && kx != k) return false;
+            kx = k;
+            xmask |= 1u << dd;
+            a.irr[dd] = nb[dd];
+        }
+    }
+    const unsigned lastinb = inblock_dirs(ch, L - 1);
+    uint32_t lastbits = 0;
+    for (int q = 0; q < 2; ++q) {
+        const int qa = cross_axis3(ax, q);
+        lastbits |= ((lastinb >> (2 * qa)) & 1u) << (2 * q);
+        lastbits |= ((lastinb >> (2 * qa + 1)) & 1u) << (2 * q + 1);
+    }
+    a.meta = meta | ((uint32_t)kx << 5) | (xmask << 10) | (lastbits << 14);
+    return true;
+}
+
+// slot of point k of a 3D chunk from its record
+__host__ __device__ __forceinline__ int rec3_slot(const Dims &d, const ChunkAddr3 &a, int k)
+{
+    return a.p0 + k * rec3_step(d, a.meta);
+}
+
+// The slots point k of a 3D chunk reads (its own and its four cross
+// neighbours) and whether the last point's cross neighbours are in the block.
+struct Rec3Slots {
+    int p, nb[4];
+    unsigned skip; // bit dd: drop the coupling toward cross neighbour dd
+};
+__host__ __device__ __forceinline__ Rec3Slots rec3_point_slots(const Dims &d, const ChunkAddr3 &a, int k)
+{
+    const uint32_t mt = a.meta;
+    const int L = mt & 31, kx = (mt >> 5) & 31;
+    const unsigned xm = k == kx ? (mt >> 10) & 15u : 0u;
+    Rec3Slots r;
+    r.p = a.p0 + k * rec3_step(d, mt);
+    r.nb[0] = (xm & 1u) ? a.irr[0] : r.p - a.s[0];
+    r.nb[1] = (xm & 2u) ? a.irr[1] : r.p + a.s[0];
+    r.nb[2] = (xm & 4u) ? a.irr[2] : r.p - a.s[1];
+    r.nb[3] = (xm & 8u) ? a.irr[3] : r.p + a.s[1];
+    r.skip = k == L - 1 ? (mt >> 14) & 15u : 0u;
+    return r;
+}
+
+// f minus the four cross couplings, from the loaded values (same order as
+// point_rhs_across: the lower cross axis first, each toward - then +)
+template <typename T>
+__host__ __device__ __forceinline__ T rec3_rhs_combine(T fp, const T (&uv)[4], const T (&cc)[4], unsigned skip)
+{
+    T r = fp;
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        const T t = cc[dd] * uv[dd];
+        r -= ((skip >> dd) & 1u) ? T(0) : t;
+    }
+    return r;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T point_rhs_rec3(const Dims &d, const ChunkAddr3 &a, const T (&cc)[4],
+                                                     const T *__restrict__ ub, const T *__restrict__ fb, int k)
+{
+    const Rec3Slots q = rec3_point_slots(d, a, k);
+    const T uv[4] = {ub[q.nb[0]], ub[q.nb[1]], ub[q.nb[2]], ub[q.nb[3]]};
+    return rec3_rhs_combine<T>(fb[q.p], uv, cc, q.skip);
+}
+
+// the chunk's four cross coefficients (3D), in the records' order
+template <typename T>
+__host__ __device__ __forceinline__ void chunk_cross_coefs3(const Coef<T> &cf, const Chunk &ch, T (&cc)[4])
+{
+    const int ax = ch.axdir >> 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a2 = cross_axis3(ax, q);
+        const int c = a2 == 0 ? ch.c0[0] : (a2 == 1 ? ch.c0[1] : ch.c0[2]);
+        cc[2 * q] = cf.base[(2 * a2) * cf.cs + c];
+        cc[2 * q + 1] = cf.base[(2 * a2 + 1) * cf.cs + c];
+    }
+}
+
 // slot of point k of a chunk
 __host__ __device__ __forceinline__ int point_index(const Dims &d, const Chunk &ch, int k)
 {

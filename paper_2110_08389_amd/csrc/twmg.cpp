@@ -147,11 +147,16 @@ struct Grid3 {
     int dim, n[3], np[3];
     long long st[3], nn;
     int layout = LAYOUT_ROW; // storage layout of the level's arrays (chunks never straddle its planes)
-    // plane of node (i, j) in a split layout (1: column-major plane), as col_plane
-    int plane(int i, int j) const
+    // plane of node (i, j[, l]) in a split layout: as col_plane in 2D (1:
+    // column-major plane), as plane3 in the 3D tweed layout
+    int plane(int i, int j, int l = 0) const
     {
         if (layout == LAYOUT_ROW) return 0;
         const int ip = std::min(i, n[0] - i), jp = std::min(j, n[1] - j);
+        if (layout == LAYOUT_TWEED3) {
+            const int lp = std::min(l, n[2] - l);
+            return (ip <= jp && ip <= lp) ? 0 : (jp <= lp ? 1 : 2);
+        }
         return layout == LAYOUT_TWEED ? (ip > jp) : (layout == LAYOUT_WIREFRAME ? (ip < jp) : 1);
     }
     void coords(long long p, int &i, int &j, int &l) const
@@ -187,8 +192,9 @@ int find_root(std::vector<int> &par, int x)
 
 // split a straight sequence of points into chunks of at most maxlen (<= CH)
 // points that each lie in one plane of the level's layout and have at most
-// one point per side whose cross neighbour is kept in the other plane (the
-// addressing record of a 2D chunk holds one such exception per side)
+// one point per side (2D) or one point in all (3D) whose cross neighbours are
+// not all kept in its plane (the addressing records hold that many
+// exceptions)
 void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, HostBlock &hb, int maxlen)
 {
     const int n = (int)pts.size();
@@ -197,9 +203,24 @@ void chunk_seq(const Grid3 &g, const std::vector<long long> &pts, int axdir, Hos
     for (int q = 0; q < n; ++q) {
         int i, j, l;
         g.coords(pts[q], i, j, l);
-        pl[q] = g.plane(i, j);
-        om[q] = g.dim == 2 && g.plane(i - qx, j - qy) != pl[q];
-        opp[q] = g.dim == 2 && g.plane(i + qx, j + qy) != pl[q];
+        pl[q] = g.plane(i, j, l);
+        if (g.dim == 2) {
+            om[q] = g.plane(i - qx, j - qy) != pl[q];
+            opp[q] = g.plane(i + qx, j + qy) != pl[q];
+        } else {
+            // 3D: one count for all four cross neighbours
+            int x = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (a == ax) continue;
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    int c[3] = {i, j, l};
+                    c[a] += sg;
+                    x |= g.plane(c[0], c[1], c[2]) != pl[q];
+                }
+            }
+            om[q] = x;
+            opp[q] = 0;
+        }
     }
     for (int s = 0; s < n;) {
         int e = s + 1, cm = om[s], cp = opp[s];
@@ -390,11 +411,11 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out, int max
                 // leg in the branch point's plane, so that no extra cut is needed
                 int i, j, l;
                 gc.coords(J, i, j, l);
-                const int pj = gc.plane(i, j);
+                const int pj = gc.plane(i, j, l);
                 auto leg_plane = [&](size_t lg) {
                     int a, b2, c2;
                     gc.coords(legs[lg].back(), a, b2, c2);
-                    return gc.plane(a, b2);
+                    return gc.plane(a, b2, c2);
                 };
                 if (leg_plane(0) != pj)
                     for (size_t lg = 1; lg < legs.size(); ++lg)
@@ -537,7 +558,8 @@ int build_blocks(const Grid3 &g, int motif, std::vector<HostBlock> &out, int max
 // longest reduced solves start early).
 struct HostTable {
     std::vector<Chunk> chunks;
-    std::vector<ChunkAddr> addrs; // 2D: addressing records in the level's layout
+    std::vector<ChunkAddr> addrs;   // 2D: addressing records in the level's layout
+    std::vector<ChunkAddr3> addrs3; // 3D: addressing records in the level's layout
     std::vector<Block> blocks;
     std::vector<WGDesc> wgs;  // the first nbig need NT lanes, the rest nts
     int nbig = 0;
@@ -1305,9 +1327,10 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
         // the kernels address a problem's array with 32-bit slots (the batch
         // offset is 64-bit): one problem's array must stay below 2^31 entries
         if (L.d.bs > (long long)INT32_MAX) return MG_EUNSUPPORTED;
-        // the 3D sweeps address every point of a chunk individually (general
-        // form), so their chunks need no cuts at the planes' borders
-        L.g.layout = L.d.layout == LAYOUT_TWEED3 ? LAYOUT_ROW : L.d.layout;
+        // chunks are cut at the planes' borders, so that each is a run of
+        // slots of one plane (3D tweed: a leg's end can be a tie node kept in
+        // the other leg's plane)
+        L.g.layout = L.d.layout;
         for (int a = 0; a < 3; ++a) L.g.st[a] = L.d.st[a];
         L.g.nn = L.d.nn;
         for (int a = 0; a < dim; ++a) {
@@ -1429,6 +1452,25 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                         std::vector<double> c64(2 * t.chunks.size());
                         for (size_t q = 0; q < t.chunks.size(); ++q)
                             chunk_cross_coefs<double>(L.hc64[adj], t.chunks[q], c64[2 * q], c64[2 * q + 1]);
+                        const std::vector<float> c32(c64.begin(), c64.end());
+                        T.cross64[adj] = h->pool.upload(c64, err);
+                        T.cross32[adj] = h->pool.upload(c32, err);
+                    }
+                } else {
+                    // 3D records and four cross coefficients per chunk, for
+                    // the chunks of the small workgroups
+                    t.addrs3.assign(t.chunks.size(), ChunkAddr3{0, 0, {0, 0}, {0, 0, 0, 0}});
+                    for (size_t wi = (size_t)t.nbig; wi < t.wgs.size(); ++wi)
+                        for (int q = t.wgs[wi].chunk0; q < t.wgs[wi].chunk0 + t.wgs[wi].nchunk; ++q)
+                            if (!make_chunk_addr3(L.d, t.chunks[q], t.addrs3[q])) return MG_EUNSUPPORTED;
+                    T.addrs3 = h->pool.upload(t.addrs3, err);
+                    for (int adj = 0; adj < 2; ++adj) {
+                        std::vector<double> c64(4 * t.chunks.size());
+                        for (size_t q = 0; q < t.chunks.size(); ++q) {
+                            double cc[4];
+                            chunk_cross_coefs3<double>(L.hc64[adj], t.chunks[q], cc);
+                            for (int e = 0; e < 4; ++e) c64[4 * q + e] = cc[e];
+                        }
                         const std::vector<float> c32(c64.begin(), c64.end());
                         T.cross64[adj] = h->pool.upload(c64, err);
                         T.cross32[adj] = h->pool.upload(c32, err);
@@ -2158,13 +2200,15 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                         // per chunk the along-axis couplings of its end points
                         // as the kernel: 2D workgroups of NT/2 lanes use the chunk
                         // records (valid in the level's own layout only)
-                        const bool rec = D.dim == 2 && D.layout == L.d.layout && (&w - &t.wgs[0]) >= t.nbig;
+                        const bool rec = D.layout == L.d.layout && (&w - &t.wgs[0]) >= t.nbig;
                         for (int ln = 0; ln < w.nchunk; ++ln) {
-                            double cm = 0, cp = 0;
-                            if (rec) chunk_cross_coefs<double>(c, chs[ln], cm, cp);
+                            double cm = 0, cp = 0, cc[4] = {0, 0, 0, 0};
+                            if (rec && D.dim == 2) chunk_cross_coefs<double>(c, chs[ln], cm, cp);
+                            if (rec && D.dim == 3) chunk_cross_coefs3<double>(c, chs[ln], cc);
                             for (int k = 0; k < chs[ln].len; ++k)
                                 pt[ln * CH + k] =
-                                    rec ? point_rhs_rec<double>(D, t.addrs[w.chunk0 + ln], cm, cp, ub, fb, k)
+                                    rec ? (D.dim == 2 ? point_rhs_rec<double>(D, t.addrs[w.chunk0 + ln], cm, cp, ub, fb, k)
+                                                      : point_rhs_rec3<double>(D, t.addrs3[w.chunk0 + ln], cc, ub, fb, k))
                                         : (D.dim == 2 ? point_rhs_across<double, 2>(D, c, ub, fb, chs[ln], k)
                                                       : point_rhs_across<double, 3>(D, c, ub, fb, chs[ln], k));
                         }
@@ -2185,8 +2229,9 @@ static int host_smooth(mg_handle *h, int lv, double *u, const double *f, int nu,
                         for (int ln = 0; ln < w.nchunk; ++ln) sweep_phase3<double>(&pt[ln * CH], ln, r, st[ln]);
                         for (int ln = 0; ln < w.nchunk; ++ln)
                             for (int k = 0; k < chs[ln].len; ++k)
-                                ub[rec ? rec_slot(D, t.addrs[w.chunk0 + ln], k) : point_index(D, chs[ln], k)] =
-                                    pt[ln * CH + k];
+                                ub[rec ? (D.dim == 2 ? rec_slot(D, t.addrs[w.chunk0 + ln], k)
+                                                     : rec3_slot(D, t.addrs3[w.chunk0 + ln], k))
+                                       : point_index(D, chs[ln], k)] = pt[ln * CH + k];
                     }
                 }
             }

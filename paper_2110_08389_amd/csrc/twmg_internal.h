@@ -65,6 +65,24 @@ struct ChunkAddr {
 };
 static_assert(sizeof(ChunkAddr) == 16, "chunk address record is 16 bytes");
 
+// Addressing record of a 3D chunk.  Point k's slot is p0 + k step, step the
+// chunk axis's stride in the chunk's plane (1 in the 3D tweed layout, whose
+// lines run along their plane's fast axis), signed by the direction.  Its
+// four neighbours across the chunk axis (the two other axes in increasing
+// order, each toward - then +) sit at -/+ s[0] and -/+ s[1], except at one
+// point (kx), whose neighbours flagged in xmask lie in other planes and are
+// read from irr.  Along a line of the 3D tweed layout only the point nearest
+// the centre can have such neighbours.  meta bits: 0-4 len, 5-9 kx (31:
+// none), 10-13 xmask, 14-17 the last point's four cross neighbours are in the
+// block, 18-19 chunk axis, 20 direction (1: increasing coordinate).
+struct ChunkAddr3 {
+    int p0;
+    uint32_t meta;
+    int s[2];
+    int irr[4];
+};
+static_assert(sizeof(ChunkAddr3) == 32, "3D chunk address record is 32 bytes");
+
 // Role of a node in the reduced-system solve.  Nodes are solved by two affine
 // scans over the workgroup: forward elimination along each segment (a leg, a
 // chain, or a ring opened at its border node), then back substitution.
@@ -201,8 +219,11 @@ template <typename T> __host__ __device__ inline Coef<T> make_coef(const T *base
 
 struct SweepTable {
     Chunk *chunks = nullptr;
-    ChunkAddr *addrs = nullptr; // 2D: per-chunk addressing records
-    double *cross64[2] = {nullptr, nullptr}; // 2D: per-chunk cross coefficients (toward -, +) [fwd, transposed]
+    ChunkAddr *addrs = nullptr;   // 2D: per-chunk addressing records
+    ChunkAddr3 *addrs3 = nullptr; // 3D: per-chunk addressing records
+    // per-chunk cross coefficients [fwd, transposed]: 2D toward -, +; 3D
+    // toward -, + along each of the two other axes
+    double *cross64[2] = {nullptr, nullptr};
     float *cross32[2] = {nullptr, nullptr};
     Block *blocks = nullptr;
     WGDesc *wgs = nullptr;
