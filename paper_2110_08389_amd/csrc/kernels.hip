@@ -1281,33 +1281,14 @@ template <int PL> __device__ __forceinline__ int margin3(const Dims &d, int i, i
     return min(o1, o2) - own;
 }
 
-// Tile t of plane PL: this thread's column of NB consecutive nodes along B,
-// op(PlaneC<PL>, f, a, b) with the first node's coordinates along F, A, B
-// (b a multiple of NB) unless the whole column lies outside the grid.  A tile
-// whose 8 corners all lie in other planes, and that does not straddle a
-// centre line n/2, is skipped whole: away from the centre lines the primed
-// coordinates are monotone along each axis inside a tile, so the plane's
-// region (an intersection of half-spaces in them) meets the tile only if it
-// holds a corner.
+// The tile of plane PL at (f0, a0, b0) (along F, A, B): this thread's column
+// of NB consecutive nodes along B, op(PlaneC<PL>, f, a, b) with the first
+// node's coordinates (b a multiple of NB) unless the whole column lies
+// outside the grid.
 template <int PL, int NB, typename Op>
-__device__ __forceinline__ void tile3_plane(const Dims &d, int t, Op &&op)
+__device__ __forceinline__ void tile3_plane(const Dims &d, int f0, int a0, int b0, Op &&op)
 {
     using X = PlaneAxes<PL>;
-    constexpr int TB = 4 * NB;
-    const int tf = (d.n[X::F] + 16) / 16, ta = (d.n[X::A] + 4) / 4;
-    const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * TB;
-    if (d.layout == LAYOUT_TWEED3) {
-        const int nf = d.n[X::F], na = d.n[X::A], nb = d.n[X::B];
-        const int f1 = min(f0 + 15, nf), a1 = min(a0 + 3, na), b1 = min(b0 + TB - 1, nb);
-        bool any = (f0 < nf / 2 && f1 > nf / 2) || (a0 < na / 2 && a1 > na / 2) || (b0 < nb / 2 && b1 > nb / 2);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            int i, j, l;
-            plane_xyz<PL>((k & 1) ? f1 : f0, (k & 2) ? a1 : a0, (k & 4) ? b1 : b0, i, j, l);
-            any = any || plane3(d, i, j, l) == PL;
-        }
-        if (!any) return;
-    }
     const int q = threadIdx.x;
     const int f = f0 + (q & 15), a = a0 + ((q >> 4) & 3), b = b0 + NB * (q >> 6);
     if (f > d.n[X::F] || a > d.n[X::A] || b > d.n[X::B]) return;
@@ -1318,26 +1299,49 @@ __device__ __forceinline__ void tile3_plane(const Dims &d, int t, Op &&op)
 // 16 along the plane's fast axis F by 4 along A by 4 NB along B, a thread
 // holding NB consecutive nodes along B (a wavefront reads four whole 128-byte
 // runs per load): the loads of a column are issued together and the values
-// its nodes share (neighbours along B, coefficients along F and A, coarse
-// values) are read once.  A tile handles only the nodes kept in its plane, so
-// the three tile families visit every node once; the row-major layout has
-// plane 0 only.  The plane is uniform per workgroup and a template argument
-// below the branch, so no coordinate is picked by a run-time axis index.
-template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int t, Op &&op)
+// its nodes share (coefficients along F and A, coarse values) are read once.
+// A tile handles only the nodes kept in its plane, so the three tile families
+// visit every node once; the row-major layout has plane 0 only.  The levels
+// carry their tile lists with each tile's plane and origin (on the split
+// layout only the tiles that hold nodes of their plane); arrays without one
+// (a caller's row-major array) decode the tile number.  The plane is uniform
+// per workgroup and a template argument below the branch, so no coordinate is
+// picked by a run-time axis index.
+template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int k, Op &&op)
 {
-    const int t0 = ptiles<0, NB>(d);
-    if (t < t0) {
-        tile3_plane<0, NB>(d, t, op);
-        return;
+    int pl, f0, a0, b0;
+    if (d.tiles) {
+        const Tile3E e = d.tiles[k];
+        pl = e.x & 3;
+        f0 = e.x >> 2;
+        a0 = e.y & 0xffff;
+        b0 = e.y >> 16;
+    } else {
+        // row-major: plane 0 only
+        const int tf = (d.n[0] + 16) / 16, ta = (d.n[1] + 4) / 4;
+        pl = 0;
+        f0 = (k % tf) * 16;
+        a0 = ((k / tf) % ta) * 4;
+        b0 = (k / (tf * ta)) * (4 * NB);
     }
-    t -= t0;
-    const int t1 = ptiles<1, NB>(d);
-    if (t < t1)
-        tile3_plane<1, NB>(d, t, op);
+    if (pl == 0)
+        tile3_plane<0, NB>(d, f0, a0, b0, op);
+    else if (pl == 1)
+        tile3_plane<1, NB>(d, f0, a0, b0, op);
     else
-        tile3_plane<2, NB>(d, t - t1, op);
+        tile3_plane<2, NB>(d, f0, a0, b0, op);
 }
-__device__ __forceinline__ int tile3_index(int it, int nt) { return (int)gridDim.x == nt ? xcd_tile(it, nt) : it; }
+// Tiles a launch visits: the level's list, else every tile of the row-major
+// layout
+template <int NB> __host__ __device__ __forceinline__ int tile3_count(const Dims &d)
+{
+    return d.tiles ? d.ntiles : ptiles<0, NB>(d);
+}
+// Tile of grid-stride iteration it: xcd_tile is a bijection of [0, nt), and
+// with a grid of a multiple of 8 workgroups (or one per tile) every iteration
+// of a workgroup stays on its XCD, which works through one contiguous range of
+// the tiles
+__device__ __forceinline__ int tile3_index(int it, int nt) { return xcd_tile(it, nt); }
 
 // The NB nodes of a column: coordinates, slots in plane PL, ok (in the grid
 // and kept in plane PL) and in (also interior)
@@ -1473,78 +1477,82 @@ __device__ __forceinline__ void defects3(const Dims &d, const Coef<T> &cf, const
 // box per fine plane of its column, so it holds fewer)
 constexpr int COL_NB = 2, COL_NB_RESTRICT = 2;
 
-// Defects of a column's nodes (0 where not interior).  When every node is
-// interior and has its six neighbours in its plane, the column's values are
-// read at the plane's strides, each neighbour along B once; otherwise every
-// node is addressed in general form.  Same summation order as defect_at.
+// Defects of a column's nodes (0 where not interior).  A node whose six
+// neighbours share its plane finds them at the plane's strides; nearer the
+// plane's border each neighbour's slot is computed in general form.  The
+// coefficients along F and A are the column's, read once, and every load is
+// issued before the arithmetic.  Same summation order as defect_at.
 template <typename T, int PL, int NB>
 __device__ __forceinline__ void col_defects(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
                                             const T *__restrict__ fb, const Col3<NB> &c, T (&out)[NB])
 {
     using X = PlaneAxes<PL>;
-    bool fast = true;
+    const int sa = stride_a<PL>(d), sb = stride_b<PL>(d);
+    // a slot whose neighbours at the plane's strides stay inside the plane,
+    // for nodes that are not interior (their result is dropped)
+    const int safe = PL * (int)d.nn + sb + sa + 1;
+    int cc[3];
+    cc[0] = c.i[0];
+    cc[1] = c.j[0];
+    cc[2] = c.l[0];
+    const int f = cc[X::F], a = cc[X::A], b = cc[X::B];
+    T uv[NB][7], fv[NB], lb[NB], hb[NB], gb[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) fast = fast && c.in[k] && margin3<PL>(d, c.i[k], c.j[k], c.l[k]) >= 2;
-    if (fast) {
-        const int sa = stride_a<PL>(d), sb = stride_b<PL>(d), p0 = c.sl[0];
-        int cc[3];
-        cc[0] = c.i[0];
-        cc[1] = c.j[0];
-        cc[2] = c.l[0];
-        const int f = cc[X::F], a = cc[X::A], b = cc[X::B];
-        T ucol[NB + 2], um[NB][2], ua[NB][2], fv[NB], lb[NB], hb[NB], gb[NB];
+    for (int k = 0; k < NB; ++k) {
+        const bool in = c.in[k];
+        const bool reg = !in || margin3<PL>(d, c.i[k], c.j[k], c.l[k]) >= 2;
+        const int p = in ? c.sl[k] : safe;
+        // neighbours toward - and + along x, y, z
+        int nb[6];
+        int st[3];
+        st[X::F] = 1;
+        st[X::A] = sa;
+        st[X::B] = sb;
+        if (reg) {
 #pragma unroll
-        for (int m = 0; m < NB + 2; ++m) ucol[m] = ub[p0 + (m - 1) * sb];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int p = p0 + k * sb;
-            um[k][0] = ub[p - 1];
-            um[k][1] = ub[p + 1];
-            ua[k][0] = ub[p - sa];
-            ua[k][1] = ub[p + sa];
-            fv[k] = fb[p];
-            lb[k] = cf.lo[X::B][b + k];
-            hb[k] = cf.hi[X::B][b + k];
-            gb[k] = cf.dg[X::B][b + k];
+            for (int ax = 0; ax < 3; ++ax) {
+                nb[2 * ax] = p - st[ax];
+                nb[2 * ax + 1] = p + st[ax];
+            }
+        } else {
+            const int i = c.i[k], j = c.j[k], l = c.l[k];
+            nb[0] = slot3(d, i - 1, j, l);
+            nb[1] = slot3(d, i + 1, j, l);
+            nb[2] = slot3(d, i, j - 1, l);
+            nb[3] = slot3(d, i, j + 1, l);
+            nb[4] = slot3(d, i, j, l - 1);
+            nb[5] = slot3(d, i, j, l + 1);
         }
-        const T lf = cf.lo[X::F][f], hf = cf.hi[X::F][f], gf = cf.dg[X::F][f];
-        const T la = cf.lo[X::A][a], ha = cf.hi[X::A][a], ga = cf.dg[X::A][a];
-        __builtin_amdgcn_sched_barrier(0);
+        uv[k][0] = ub[p];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            T lo[3], hi[3], dg[3], vm[3], vp[3];
-            lo[X::F] = lf;
-            hi[X::F] = hf;
-            dg[X::F] = gf;
-            vm[X::F] = um[k][0];
-            vp[X::F] = um[k][1];
-            lo[X::A] = la;
-            hi[X::A] = ha;
-            dg[X::A] = ga;
-            vm[X::A] = ua[k][0];
-            vp[X::A] = ua[k][1];
-            lo[X::B] = lb[k];
-            hi[X::B] = hb[k];
-            dg[X::B] = gb[k];
-            vm[X::B] = ucol[k];
-            vp[X::B] = ucol[k + 2];
-            T sum = lo[0] * vm[0] + hi[0] * vp[0];
-            sum += lo[1] * vm[1] + hi[1] * vp[1];
-            T g = dg[0] + dg[1];
-            sum += lo[2] * vm[2] + hi[2] * vp[2];
-            g += dg[2];
-            out[k] = fv[k] - (sum + g * ucol[k + 1]);
-        }
-    } else {
-        // one node at a time: the general form holds few values in flight
+        for (int m = 0; m < 6; ++m) uv[k][m + 1] = ub[nb[m]];
+        fv[k] = fb[p];
+        const int bk = min(b + k, d.n[X::B]);
+        lb[k] = cf.lo[X::B][bk];
+        hb[k] = cf.hi[X::B][bk];
+        gb[k] = cf.dg[X::B][bk];
+    }
+    const T lf = cf.lo[X::F][f], hf = cf.hi[X::F][f], gf = cf.dg[X::F][f];
+    const T la = cf.lo[X::A][a], ha = cf.hi[X::A][a], ga = cf.dg[X::A][a];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int i1[1] = {c.i[k]}, j1[1] = {c.j[k]}, l1[1] = {c.l[k]};
-            const bool in1[1] = {c.in[k]};
-            T o1[1];
-            defects3<T, 1>(d, cf, ub, fb, i1, j1, l1, in1, o1);
-            out[k] = o1[0];
-        }
+    for (int k = 0; k < NB; ++k) {
+        T lo[3], hi[3], dg[3];
+        lo[X::F] = lf;
+        hi[X::F] = hf;
+        dg[X::F] = gf;
+        lo[X::A] = la;
+        hi[X::A] = ha;
+        dg[X::A] = ga;
+        lo[X::B] = lb[k];
+        hi[X::B] = hb[k];
+        dg[X::B] = gb[k];
+        T sum = lo[0] * uv[k][1] + hi[0] * uv[k][2];
+        sum += lo[1] * uv[k][3] + hi[1] * uv[k][4];
+        T g = dg[0] + dg[1];
+        sum += lo[2] * uv[k][5] + hi[2] * uv[k][6];
+        g += dg[2];
+        out[k] = c.in[k] ? fv[k] - (sum + g * uv[k][0]) : T(0);
     }
 }
 
@@ -1554,7 +1562,7 @@ __global__ void __launch_bounds__(256) k_residual3(Dims d, Coef<T> cf, const T *
                                                    const T *__restrict__ f, T *__restrict__ r)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3<COL_NB>(d);
+    const int nt = tile3_count<COL_NB>(d);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
         tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
             constexpr int PL = decltype(plc)::value;
@@ -1575,7 +1583,7 @@ __global__ void __launch_bounds__(256) k_resnorm3(Dims d, Coef<T> cf, const T *_
                                                   double *__restrict__ partial)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3<COL_NB>(d);
+    const int nt = tile3_count<COL_NB>(d);
     double m = 0.0;
     bool nan = false;
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
@@ -1694,7 +1702,7 @@ __global__ void __launch_bounds__(256) k_prolong3(Dims fd, Dims cd, const T *__r
 {
     T *ub = u + (long long)blockIdx.y * fd.bs;
     const T *eb = ec + (long long)blockIdx.y * cd.bs;
-    const int nt = tiles3<COL_NB>(fd);
+    const int nt = tile3_count<COL_NB>(fd);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
         tile3_visit<COL_NB>(fd, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
             constexpr int PL = decltype(plc)::value;
@@ -1788,7 +1796,7 @@ __global__ void __launch_bounds__(256) k_fw_restrict3(Dims fd, Dims cd, const T 
     const T *db = dr + (long long)blockIdx.y * fd.bs;
     const long long cboff = (long long)blockIdx.y * cd.bs;
     constexpr int NB = COL_NB_RESTRICT;
-    const int nt = tiles3<NB>(cd);
+    const int nt = tile3_count<NB>(cd);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
         tile3_visit<NB>(cd, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
             constexpr int PL = decltype(plc)::value;
@@ -1801,7 +1809,7 @@ __global__ void __launch_bounds__(256) k_fw_restrict3(Dims fd, Dims cd, const T 
 __global__ void __launch_bounds__(256) k_ir_update3(Dims d, double *__restrict__ u, const float *__restrict__ e)
 {
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tiles3<COL_NB>(d);
+    const int nt = tile3_count<COL_NB>(d);
     for (int it = blockIdx.x; it < nt; it += gridDim.x)
         tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
             constexpr int PL = decltype(plc)::value;
@@ -1820,11 +1828,54 @@ __global__ void __launch_bounds__(256) k_ir_update3(Dims d, double *__restrict__
         });
 }
 
-// workgroups of a 3D tile launch: one per tile up to 65535
-template <int NB> static int tile3_grid(const Dims &d)
+// workgroups of a 3D tile launch: one per tile
+template <int NB> static int tile3_grid(const Dims &d) { return tile3_count<NB>(d); }
+
+// host: whether tile t of plane pl holds nodes of its plane.  Away from the
+// centre lines n/2 the primed coordinates are monotone along each axis inside
+// a tile, so the plane's region (an intersection of half-spaces in them)
+// meets the tile only if it holds one of the tile's corners; a tile that
+// straddles a centre line is kept.
+template <int PL, int NB> static bool tile3_active(const Dims &d, int t)
 {
-    const int nt = tiles3<NB>(d);
-    return nt < 65535 ? nt : 65535;
+    using X = PlaneAxes<PL>;
+    constexpr int TB = 4 * NB;
+    const int tf = (d.n[X::F] + 16) / 16, ta = (d.n[X::A] + 4) / 4;
+    const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * TB;
+    const int nf = d.n[X::F], na = d.n[X::A], nb = d.n[X::B];
+    const int f1 = std::min(f0 + 15, nf), a1 = std::min(a0 + 3, na), b1 = std::min(b0 + TB - 1, nb);
+    if ((f0 < nf / 2 && f1 > nf / 2) || (a0 < na / 2 && a1 > na / 2) || (b0 < nb / 2 && b1 > nb / 2)) return true;
+    for (int k = 0; k < 8; ++k) {
+        int c[3];
+        c[X::F] = (k & 1) ? f1 : f0;
+        c[X::A] = (k & 2) ? a1 : a0;
+        c[X::B] = (k & 4) ? b1 : b0;
+        if (plane3(d, c[0], c[1], c[2]) == PL) return true;
+    }
+    return false;
+}
+
+std::vector<Tile3E> tile3_list(const Dims &d)
+{
+    static_assert(COL_NB == COL_NB_RESTRICT, "one tile list serves every 3D stencil kernel");
+    std::vector<Tile3E> out;
+    const bool split = d.layout == LAYOUT_TWEED3;
+    auto add = [&](auto plc) {
+        constexpr int PL = decltype(plc)::value;
+        using X = PlaneAxes<PL>;
+        const int tf = (d.n[X::F] + 16) / 16, ta = (d.n[X::A] + 4) / 4, nt = ptiles<PL, COL_NB>(d);
+        for (int t = 0; t < nt; ++t) {
+            if (split && !tile3_active<PL, COL_NB>(d, t)) continue;
+            const int f0 = (t % tf) * 16, a0 = ((t / tf) % ta) * 4, b0 = (t / (tf * ta)) * (4 * COL_NB);
+            out.push_back(Tile3E{PL | (f0 << 2), a0 | (b0 << 16)});
+        }
+    };
+    add(PlaneC<0>());
+    if (split) {
+        add(PlaneC<1>());
+        add(PlaneC<2>());
+    }
+    return out;
 }
 
 template <typename T>
@@ -2243,7 +2294,8 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
         if (gx > nt) gx = nt;
         hipLaunchKernelGGL((k_resnorm_tile<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     } else {
-        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
+        if (gx >= tile3_count<COL_NB>(d)) gx = tile3_count<COL_NB>(d);
+        else if (gx >= 8) gx &= ~7; // a multiple of 8: iterations stay on their XCD
         hipLaunchKernelGGL((k_resnorm3<T, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
@@ -2263,7 +2315,8 @@ hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const dou
         hipLaunchKernelGGL((k_resnorm_tile<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32,
                            partial);
     } else {
-        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
+        if (gx >= tile3_count<COL_NB>(d)) gx = tile3_count<COL_NB>(d);
+        else if (gx >= 8) gx &= ~7; // a multiple of 8: iterations stay on their XCD
         hipLaunchKernelGGL((k_resnorm3<double, true>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, r32, partial);
     }
     hipLaunchKernelGGL(k_max_final, dim3(batch), dim3(MAXF_NT), 0, s, partial, gx, out);
@@ -2321,7 +2374,8 @@ hipError_t launch_resnorm_noalloc(const Dims &d, const Coef<double> &c, const do
         hipLaunchKernelGGL((k_resnorm_tile<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     } else {
-        if (gx > tiles3<COL_NB>(d)) gx = tiles3<COL_NB>(d);
+        if (gx >= tile3_count<COL_NB>(d)) gx = tile3_count<COL_NB>(d);
+        else if (gx >= 8) gx &= ~7; // a multiple of 8: iterations stay on their XCD
         hipLaunchKernelGGL((k_resnorm3<double, false>), dim3(gx, batch), dim3(256), 0, s, d, c, u, f, nullptr,
                            partial);
     }

@@ -1393,6 +1393,14 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             L.c32[o] = make_coef<float>(p32 ? p32 + COEF_PAD : nullptr, cs);
             L.hc64[o] = make_coef<double>(L.hblk[o].data(), cs);
         }
+        // the 3D stencil kernels visit only the tiles that hold nodes of
+        // their plane
+        if (dim == 3) {
+            const std::vector<Tile3E> tl = tile3_list(L.d);
+            L.d.tiles = h->pool.upload(tl, err);
+            L.d.ntiles = (int)tl.size();
+            if (err) return err;
+        }
     }
     // block tables for every level that is smoothed
     for (int l = 0; l + 1 < nl; ++l) {
@@ -1726,6 +1734,8 @@ Dims row_dims(const Dims &d)
     Dims r = d;
     r.layout = LAYOUT_ROW;
     r.bs = r.nn;
+    r.tiles = nullptr;
+    r.ntiles = 0;
     return r;
 }
 

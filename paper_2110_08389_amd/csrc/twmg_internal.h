@@ -156,6 +156,16 @@ struct Dims {
     long long nn;      // nodes per problem
     int layout;        // Layout
     long long bs;      // array length per problem (batch stride): nn, 2 nn (2D split), 3 nn (3D split)
+    // 3D levels: the tiles the 3D stencil kernels visit (device list of
+    // ntiles entries, Tile3E; on the split layout only the tiles that hold
+    // nodes of their plane); null: every tile of the row-major layout
+    const struct Tile3E *tiles = nullptr;
+    int ntiles = 0;
+};
+// A tile of the 3D stencil kernels: x = plane | (first F coordinate << 2),
+// y = first A coordinate | (first B coordinate << 16)
+struct Tile3E {
+    int x, y;
 };
 
 // split layouts: is node (i, j) stored in plane C?
@@ -333,6 +343,9 @@ hipError_t launch_resnorm(const Dims &d, const Coef<T> &c, const T *u, const T *
 hipError_t launch_resnorm_to_f32(const Dims &d, const Coef<double> &c, const double *u, const double *f, float *r32,
                                  double *partial, int npart, double *out, int batch, hipStream_t s);
 hipError_t launch_ir_update(const Dims &d, double *u, const float *e, int batch, hipStream_t s);
+// the tiles of the 3D stencil kernels on a 3D level (for Dims::tiles): on the
+// split layout those that hold nodes of their plane
+std::vector<Tile3E> tile3_list(const Dims &d);
 hipError_t launch_set_boundary(const Dims &d, double *u, const double *bc, int zero_interior, int batch,
                                hipStream_t s);
 template <typename T> hipError_t launch_fill(T *p, long long n, T v, hipStream_t s);
