@@ -1629,70 +1629,77 @@ __device__ __forceinline__ T prolong3_at(const Dims &cd, const T *eb, int i, int
     return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
 }
 
-// u += P e_c over a column of fine nodes (b even).  When every node is
-// interior and the coarse box the column interpolates from (2 x 2 across,
-// NB/2 + 1 along B) lies in one coarse plane, the box is read once at that
-// plane's strides; otherwise each node is interpolated as prolong3_at.  Same
-// arithmetic as prolong_at.
+// u += P e_c over a column of fine nodes (b even).  The column interpolates
+// from a coarse box of 2 x 2 across by NB/2 + 1 along B, read once: at the
+// strides of one coarse plane when the box lies in it, otherwise with every
+// slot in general form.  Same arithmetic as prolong_at.
 template <typename T, int PL, int NB>
 __device__ __forceinline__ void col_prolong(const Dims &fd, const Dims &cd, const T *__restrict__ eb,
                                             T *__restrict__ ub, const Col3<NB> &c, int f, int a, int b)
 {
     using X = PlaneAxes<PL>;
     constexpr int MB = NB / 2 + 1;
-    bool all_in = true;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) all_in = all_in && c.in[k];
+    // the box's first corner (coarse coordinates along F, A, B), clamped into
+    // the coarse grid for columns that reach past the fine interior (their
+    // values are not used)
+    const int F0 = min(f >> 1, cd.n[X::F] - 1), A0 = min(a >> 1, cd.n[X::A] - 1),
+              B0 = min(b >> 1, cd.n[X::B] - (MB - 1));
     int I0, J0, K0;
-    plane_xyz<PL>(f >> 1, a >> 1, b >> 1, I0, J0, K0);
+    plane_xyz<PL>(F0, A0, B0, I0, J0, K0);
     const P3i q = p3i_at(cd, I0, J0, K0);
-    if (all_in && q.margin >= 2 * (MB - 1) + 1 && q.margin >= 3) {
-        int st[3];
-        st[0] = q.sx;
-        st[1] = q.sy;
-        st[2] = q.sz;
-        const int sF = st[X::F], sA = st[X::A], sB = st[X::B];
-        T cv[MB][2][2], uv[NB];
+    const bool reg = q.margin >= 2 * (MB - 1) + 1 && q.margin >= 3;
+    int st[3];
+    st[0] = q.sx;
+    st[1] = q.sy;
+    st[2] = q.sz;
+    const int sF = st[X::F], sA = st[X::A], sB = st[X::B];
+    int slot[MB][2][2];
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int ia = 0; ia < 2; ++ia)
+        for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-                for (int iff = 0; iff < 2; ++iff) cv[m][ia][iff] = eb[q.p + m * sB + ia * sA + iff * sF];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) uv[k] = ub[c.sl[k]];
-        __builtin_amdgcn_sched_barrier(0);
-        // equal end indices (the fine coordinate is even) per x, y, z
-        bool eqF = !(f & 1), eqA = !(a & 1);
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            bool eq[3];
-            eq[X::F] = eqF;
-            eq[X::A] = eqA;
-            eq[X::B] = !(k & 1);
-            // coarse value at selectors (sx, sy, sz) in {0, 1}: index 0 is
-            // the lower end, 1 the upper
-            auto cval = [&](int sx, int sy, int sz) -> T {
-                int sel[3];
-                sel[0] = sx;
-                sel[1] = sy;
-                sel[2] = sz;
-                const int mb = sel[X::B] ? (k + 1) >> 1 : k >> 1;
-                return cv[mb][sel[X::A]][sel[X::F]];
-            };
-            T pl2[2];
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const T r0 = eq[0] ? cval(0, 0, kk) : T(0.5) * (cval(0, 0, kk) + cval(1, 0, kk));
-                const T r1 = eq[0] ? cval(0, 1, kk) : T(0.5) * (cval(0, 1, kk) + cval(1, 1, kk));
-                pl2[kk] = eq[1] ? r0 : T(0.5) * (r0 + r1);
+            for (int iff = 0; iff < 2; ++iff) {
+                int I, J, K;
+                plane_xyz<PL>(F0 + iff, A0 + ia, B0 + m, I, J, K);
+                slot[m][ia][iff] = reg ? q.p + m * sB + ia * sA + iff * sF : slot3(cd, I, J, K);
             }
-            ub[c.sl[k]] = uv[k] + (eq[2] ? pl2[0] : T(0.5) * (pl2[0] + pl2[1]));
-        }
-    } else {
+    T cv[MB][2][2], uv[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (c.in[k]) ub[c.sl[k]] += prolong3_at<T>(cd, eb, c.i[k], c.j[k], c.l[k]);
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+            for (int iff = 0; iff < 2; ++iff) cv[m][ia][iff] = eb[slot[m][ia][iff]];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) uv[k] = ub[c.in[k] ? c.sl[k] : c.sl[0]];
+    __builtin_amdgcn_sched_barrier(0);
+    // equal end indices (the fine coordinate is even) per x, y, z
+    const bool eqF = !(f & 1), eqA = !(a & 1);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        bool eq[3];
+        eq[X::F] = eqF;
+        eq[X::A] = eqA;
+        eq[X::B] = !(k & 1);
+        // coarse value at selectors (sx, sy, sz) in {0, 1}: index 0 is the
+        // lower end, 1 the upper
+        auto cval = [&](int sx, int sy, int sz) -> T {
+            int sel[3];
+            sel[0] = sx;
+            sel[1] = sy;
+            sel[2] = sz;
+            const int mb = sel[X::B] ? (k + 1) >> 1 : k >> 1;
+            return cv[mb][sel[X::A]][sel[X::F]];
+        };
+        T pl2[2];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const T r0 = eq[0] ? cval(0, 0, kk) : T(0.5) * (cval(0, 0, kk) + cval(1, 0, kk));
+            const T r1 = eq[0] ? cval(0, 1, kk) : T(0.5) * (cval(0, 1, kk) + cval(1, 1, kk));
+            pl2[kk] = eq[1] ? r0 : T(0.5) * (r0 + r1);
+        }
+        if (c.in[k]) ub[c.sl[k]] = uv[k] + (eq[2] ? pl2[0] : T(0.5) * (pl2[0] + pl2[1]));
     }
 }
 
