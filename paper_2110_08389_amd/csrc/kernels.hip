@@ -1237,10 +1237,6 @@ template <int PL, int NB> __host__ __device__ __forceinline__ int ptiles(const D
     using X = PlaneAxes<PL>;
     return ((d.n[X::F] + 16) / 16) * ((d.n[X::A] + 4) / 4) * ((d.n[X::B] + 4 * NB) / (4 * NB));
 }
-template <int NB> __host__ __device__ __forceinline__ int tiles3(const Dims &d)
-{
-    return d.layout == LAYOUT_TWEED3 ? ptiles<0, NB>(d) + ptiles<1, NB>(d) + ptiles<2, NB>(d) : ptiles<0, NB>(d);
-}
 template <int PL> __device__ __forceinline__ int slot_in_plane(const Dims &d, int i, int j, int l)
 {
     const int S0 = d.n[0] + 1, S1 = d.n[1] + 1, S2 = d.n[2] + 1, nn = (int)d.nn;
@@ -1407,72 +1403,6 @@ __device__ __forceinline__ P3i p3i_at(const Dims &d, int i, int j, int l)
 }
 __device__ __forceinline__ int slot3(const Dims &d, int i, int j, int l) { return p3i_at(d, i, j, l).p; }
 
-// the slots a 7-point defect at (i, j, l) reads: itself, x-, x+, y-, y+, z-, z+
-struct Nb7 {
-    int p, nb[6];
-};
-__device__ __forceinline__ Nb7 nb7_at(const Dims &d, int i, int j, int l)
-{
-    const P3i q = p3i_at(d, i, j, l);
-    Nb7 r;
-    r.p = q.p;
-    if (q.margin >= 2) {
-        r.nb[0] = q.p - q.sx;
-        r.nb[1] = q.p + q.sx;
-        r.nb[2] = q.p - q.sy;
-        r.nb[3] = q.p + q.sy;
-        r.nb[4] = q.p - q.sz;
-        r.nb[5] = q.p + q.sz;
-    } else {
-        r.nb[0] = slot3(d, i - 1, j, l);
-        r.nb[1] = slot3(d, i + 1, j, l);
-        r.nb[2] = slot3(d, i, j - 1, l);
-        r.nb[3] = slot3(d, i, j + 1, l);
-        r.nb[4] = slot3(d, i, j, l - 1);
-        r.nb[5] = slot3(d, i, j, l + 1);
-    }
-    return r;
-}
-
-// Defects of NB nodes at once: every load is issued before any arithmetic.
-// Nodes with in[k] false give 0 (their loads are clamped to node (1, 1, 1)).
-// Same summation order as defect_at.
-template <typename T, int NB>
-__device__ __forceinline__ void defects3(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
-                                         const T *__restrict__ fb, const int (&i)[NB], const int (&j)[NB],
-                                         const int (&l)[NB], const bool (&in)[NB], T (&out)[NB])
-{
-    T uv[NB][7], fv[NB], c[NB][9];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const int ic = in[k] ? i[k] : 1, jc = in[k] ? j[k] : 1, lc = in[k] ? l[k] : 1;
-        const Nb7 s = nb7_at(d, ic, jc, lc);
-        uv[k][0] = ub[s.p];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) uv[k][m + 1] = ub[s.nb[m]];
-        fv[k] = fb[s.p];
-        c[k][0] = cf.lo[0][ic];
-        c[k][1] = cf.hi[0][ic];
-        c[k][2] = cf.lo[1][jc];
-        c[k][3] = cf.hi[1][jc];
-        c[k][4] = cf.lo[2][lc];
-        c[k][5] = cf.hi[2][lc];
-        c[k][6] = cf.dg[0][ic];
-        c[k][7] = cf.dg[1][jc];
-        c[k][8] = cf.dg[2][lc];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        T sum = c[k][0] * uv[k][1] + c[k][1] * uv[k][2];
-        sum += c[k][2] * uv[k][3] + c[k][3] * uv[k][4];
-        T dg = c[k][6] + c[k][7];
-        sum += c[k][4] * uv[k][5] + c[k][5] * uv[k][6];
-        dg += c[k][8];
-        out[k] = in[k] ? fv[k] - (sum + dg * uv[k][0]) : T(0);
-    }
-}
-
 // nodes per thread of the 3D stencil kernels (the restriction reads a 3 x 3
 // box per fine plane of its column, so it holds fewer)
 constexpr int COL_NB = 2, COL_NB_RESTRICT = 2;
@@ -1605,29 +1535,6 @@ __global__ void __launch_bounds__(256) k_resnorm3(Dims d, Coef<T> cf, const T *_
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
 }
 
-// interpolated coarse correction (as prolong_at) with 32-bit slots: the
-// 2 x 2 x 2 coarse box at fixed offsets in the plane of its first corner when
-// that corner lies 3 or more inside it
-template <typename T>
-__device__ __forceinline__ T prolong3_at(const Dims &cd, const T *eb, int i, int j, int l)
-{
-    const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
-    const int K0 = l >> 1, K1 = (l + 1) >> 1;
-    const P3i q0 = p3i_at(cd, I0, J0, K0);
-    const bool fast = q0.margin >= 3;
-    auto cval = [&](int I, int J, int K) -> T {
-        return eb[fast ? q0.p + (I - I0) * q0.sx + (J - J0) * q0.sy + (K - K0) * q0.sz : slot3(cd, I, J, K)];
-    };
-    T pl[2];
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        const int K = kk ? K1 : K0;
-        const T r0 = (I0 == I1) ? cval(I0, J0, K) : T(0.5) * (cval(I0, J0, K) + cval(I1, J0, K));
-        const T r1 = (I0 == I1) ? cval(I0, J1, K) : T(0.5) * (cval(I0, J1, K) + cval(I1, J1, K));
-        pl[kk] = (J0 == J1) ? r0 : T(0.5) * (r0 + r1);
-    }
-    return (K0 == K1) ? pl[0] : T(0.5) * (pl[0] + pl[1]);
-}
 
 // u += P e_c over a column of fine nodes (b even).  The column interpolates
 // from a coarse box of 2 x 2 across by NB/2 + 1 along B, read once: at the
