@@ -407,7 +407,9 @@ template <typename T>
 __host__ __device__ __forceinline__ void chunk_cross_coefs(const Coef<T> &cf, const Chunk &ch, T &cm, T &cp)
 {
     const int a2 = 1 - (ch.axdir >> 1);
-    const int cc = ch.c0[a2];
+    // (a select, not ch.c0[a2]: a run-time index would put the chunk in
+    // private memory)
+    const int cc = a2 == 0 ? ch.c0[0] : ch.c0[1];
     cm = cf.base[(2 * a2) * cf.cs + cc];
     cp = cf.base[(2 * a2 + 1) * cf.cs + cc];
 }
