@@ -1668,7 +1668,15 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
     // largest of these ratios is below tol (a problem whose initial defect is
     // zero is already solved and takes no part)
     std::vector<double> d0(B), d(B);
-    HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
+    // With refinement every defect pass also leaves the defect rounded to
+    // FP32 in L.f32: the right-hand side of the next step's FP32 cycle (the
+    // same pass gives the norm, bitwise as launch_resnorm)
+    auto defect_norm = [&]() -> hipError_t {
+        return ir ? launch_resnorm_to_f32(L.d, L.c64[adj], u, f, L.f32, h->partial, NORM_PARTS, h->normv, B,
+                                          h->stream)
+                  : launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream);
+    };
+    HIPCHK(defect_norm());
     if ((rc = read_norms(h, d0.data()))) return rc;
     int k = 0, status = MG_OK;
     double rel = 0.0, d0max = 0.0;
@@ -1683,16 +1691,15 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
         status = MG_ENOTCONV;
         while (k < h->opt.max_cycles) {
             if (ir) {
-                // r = f - A u (FP64) rounded to FP32; e = FP32 cycle on A e = r from 0; u += e
-                HIPCHK(launch_resnorm_to_f32(L.d, L.c64[adj], u, f, L.f32, h->partial, NORM_PARTS, h->normv, B,
-                                             h->stream));
+                // e = FP32 cycle on A e = r from 0, r = f - A u (FP64, from the
+                // last defect pass) rounded to FP32; u += e
                 HIPCHK(launch_fill<float>(L.u32, L.d.bs * B, 0.0f, h->stream));
                 if ((rc = cycle<float>(h, 0, L.u32, L.f32, adj))) return rc;
                 HIPCHK(launch_ir_update(L.d, u, L.u32, B, h->stream));
             } else {
                 if ((rc = cycle<double>(h, 0, u, f, adj))) return rc;
             }
-            HIPCHK(launch_resnorm<double>(L.d, L.c64[adj], u, f, h->partial, NORM_PARTS, h->normv, B, h->stream));
+            HIPCHK(defect_norm());
             if ((rc = read_norms(h, d.data()))) return rc;
             rel = 0.0;
             bool bad = false;
