@@ -1967,9 +1967,27 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
     __shared__ T s_rs[TAIL_NT], s_rn[TAIL_NT], s_dl[TAIL_NT], s_x[TAIL_NT];
     __shared__ T s_a[TAIL_NT / 64], s_b[TAIL_NT / 64];
     {
+        // the copies issue a batch of loads per thread before storing any (a
+        // plain loop waited for each load: one round trip per 16 bytes)
         const uint4 *src = reinterpret_cast<const uint4 *>(P.image);
         uint4 *dst = reinterpret_cast<uint4 *>(s_mem);
-        for (int q = threadIdx.x; q < P.image_bytes / 16; q += blockDim.x) dst[q] = src[q];
+        const int n16 = P.image_bytes / 16;
+        constexpr int CB = 16;
+        // (positions past the end load and store the batch's first one again:
+        // no branch separates the loads from each other)
+        for (int q0 = threadIdx.x; q0 < n16; q0 += CB * TAIL_NT) {
+            uint4 v[CB];
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const int q = q0 + k * TAIL_NT;
+                v[k] = src[q < n16 ? q : q0];
+            }
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const int q = q0 + k * TAIL_NT;
+                dst[q < n16 ? q : q0] = v[k];
+            }
+        }
     }
     __syncthreads();
     const TailLevel *lev = reinterpret_cast<const TailLevel *>(s_mem + P.lev_off);
@@ -1981,9 +1999,22 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_cycle(TailPlan<T> P, T *__rest
     const T *fg = f + boff;
     {
         T *u0 = arr(lev[0].uoff), *f0 = arr(lev[0].foff);
-        for (int q = threadIdx.x; q < (int)P.nn0; q += blockDim.x) {
-            u0[q] = ug[q];
-            f0[q] = fg[q];
+        const int nn = (int)P.nn0;
+        constexpr int CB = 8;
+        for (int q0 = threadIdx.x; q0 < nn; q0 += CB * TAIL_NT) {
+            T uv[CB], fv[CB];
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const int q = q0 + k * TAIL_NT, qc = q < nn ? q : q0;
+                uv[k] = ug[qc];
+                fv[k] = fg[qc];
+            }
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const int q = q0 + k * TAIL_NT, qc = q < nn ? q : q0;
+                u0[qc] = uv[k];
+                f0[qc] = fv[k];
+            }
         }
     }
     __syncthreads();
