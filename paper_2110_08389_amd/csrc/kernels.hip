@@ -500,21 +500,22 @@ __device__ __forceinline__ void chunk_coef_window(const T *__restrict__ P, int c
     }
 }
 
-// The work of one workgroup descriptor w; all NT lanes of the workgroup must
-// call it.  REC (2D, NT/2-lane workgroups): the points are addressed through
-// the chunks' precomputed records (addrs), and each wavefront gathers the
-// points of its own 64 chunks together with their along-axis coefficients,
-// which reach the lanes that own the chunks through the wavefront's rows of
-// the staging buffer; otherwise in general form, each lane loading its
-// chunk's coefficients itself.
-// C: the chunk capacity (CH, or fewer for the small levels' short chunks;
-// records path only).
+// addressing record type of a chunk, by dimension
 template <int DIM> struct RecOf {
     using type = ChunkAddr;
 };
 template <> struct RecOf<3> {
     using type = ChunkAddr3;
 };
+
+// The work of one workgroup descriptor w; all NT lanes of the workgroup must
+// call it.  REC (workgroups of at most NT/2 lanes, 2D and 3D): the points are
+// addressed through the chunks' precomputed records (addrs), and each
+// wavefront gathers the points of its own 64 chunks; otherwise (the NT-lane
+// workgroups of the largest blocks) in general form, each point's slots
+// computed from its coordinates.
+// C: the chunk capacity (CH, or fewer for the small levels' short chunks;
+// records path only).
 
 template <typename T, int DIM, int NT, bool DOFF, bool REC, int C = CH>
 __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__restrict__ ub,
@@ -762,7 +763,7 @@ __device__ __forceinline__ void sweep_wg(const Dims &d, const Coef<T> &cf, T *__
 }
 
 // DOFF: FP64 forward operator (diagonal from the off-diagonal coefficients);
-// 2D workgroups of NT/2 lanes address their points through the records
+// workgroups of at most NT/2 lanes address their points through the records
 // Workgroups of at most NT/2 lanes: at least three waves per SIMD, so at most
 // 168 VGPRs per lane
 template <typename T, int DIM, int NT, bool DOFF, int C = CH>
