@@ -638,9 +638,11 @@ void pack(std::vector<const HostBlock *> bl, HostTable &t, bool narrow = false)
         // Workgroups are handed to the 8 XCDs round-robin in index order.
         // Number them so that consecutive entries of the list (blocks of
         // neighbouring labels, which read the same cache lines) share an XCD
-        // and its L2: within each group of 256, entry w goes to XCD w/ceil(size/8).
+        // and its L2: entry w goes to XCD w/ceil(size/8), so each XCD works
+        // through one contiguous eighth of the list (groups of 256 entries
+        // per XCD round were 0.4% slower at 4097^2).
         {
-            const int n = (int)(t.wgs.size() - w0), G = 256;
+            const int n = (int)(t.wgs.size() - w0), G = n > 0 ? n : 1;
             std::vector<WGDesc> out(n);
             for (int g0 = 0; g0 < n; g0 += G) {
                 const int s = std::min(G, n - g0), q = (s + 7) / 8;
