@@ -844,8 +844,10 @@ struct mg_handle {
     char *ws = nullptr;
     char *dscr = nullptr; // 3D split levels: defect scratch of the restriction (one fine array, FP64 or FP32)
     bool ws_owned = false;
-    // coarse-level kernel: levels tail_lv .. nlev-1 run in one workgroup per problem
+    // coarse-level kernel: levels tail_lv .. nlev-1 run in one workgroup per
+    // problem; one launch runs tail_reps visits of their sub-cycle
     int tail_lv = -1;
+    int tail_reps = 1;
     void *tail_img[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}}; // [FP64, FP32][forward, transposed]
     TailPlan<double> tail64[2];
     TailPlan<float> tail32[2];
@@ -1057,11 +1059,14 @@ size_t align16(size_t n) { return (n + 15) & ~size_t(15); }
 // Builds the LDS image of levels lt .. nlev-1 for type T and direction adj;
 // returns the LDS bytes the kernel needs (image + u, f + scratch).
 template <typename T>
-size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char> &img, TailPlan<T> &plan)
+size_t tail_image(const mg_handle *h, int lt, int adj, std::vector<unsigned char> &img, TailPlan<T> &plan,
+                  int reps = 1)
 {
     const int nt = h->nlev - lt, dim = h->grid.dim;
     std::vector<TailOp> ops;
-    tail_ops_rec(h, lt, lt, adj, h->tail_map_lv[sizeof(T) == 8 ? 0 : 1], ops);
+    // reps sub-cycles in a row from the same right-hand side (the gamma
+    // visits of a W-cycle, in one launch)
+    for (int r = 0; r < reps; ++r) tail_ops_rec(h, lt, lt, adj, h->tail_map_lv[sizeof(T) == 8 ? 0 : 1], ops);
     ImageBuf I;
     std::vector<TailLevel> tl(nt);
     std::memset(tl.data(), 0, tl.size() * sizeof(TailLevel));
@@ -1137,6 +1142,7 @@ void free_tail(mg_handle *h)
             p = nullptr;
         }
     h->tail_lv = -1;
+    h->tail_reps = 1;
     h->tail_map_lv[0] = h->tail_map_lv[1] = -1;
 }
 
@@ -1242,10 +1248,19 @@ int build_tail(mg_handle *h)
     }
     h->tail_map_lv[0] = lm[0];
     h->tail_map_lv[1] = lm[1];
+    // entered from a finer level, the kernel runs that level's gamma visits
+    // of its sub-cycle in one launch (the first leaves u in LDS for the next)
+    // (if the longer operation list still fits the LDS budget)
+    int reps = lt > 0 ? std::max(h->opt.gamma, 1) : 1;
+    if (reps > 1) {
+        std::vector<unsigned char> img;
+        TailPlan<double> p;
+        if (tail_image<double>(h, lt, 0, img, p, reps) > (size_t)TAIL_BYTES) reps = 1;
+    }
     for (int adj = 0; adj < 2; ++adj) {
         std::vector<unsigned char> i64, i32;
-        tail_image<double>(h, lt, adj, i64, h->tail64[adj]);
-        tail_image<float>(h, lt, adj, i32, h->tail32[adj]);
+        tail_image<double>(h, lt, adj, i64, h->tail64[adj], reps);
+        tail_image<float>(h, lt, adj, i32, h->tail32[adj], reps);
         if (lm[0] >= 0) {
             h->tail64[adj].map = (const double *)h->tail_map[0][adj];
             h->tail64[adj].map_nu = (int)unknowns(lm[0]);
@@ -1265,6 +1280,7 @@ int build_tail(mg_handle *h)
         h->tail32[adj].image = (const unsigned char *)h->tail_img[1][adj];
     }
     h->tail_lv = lt;
+    h->tail_reps = reps;
     return MG_OK;
 }
 
@@ -1637,7 +1653,9 @@ template <typename T> int cycle(mg_handle *h, int lv, T *u, const T *f, int adj)
     Level &C = h->lev[lv + 1];
     T *uc = lev_u<T>(C), *fc = lev_f<T>(C);
     HIPCHK(launch_residual_restrict<T>(L.d, C.d, coefs<T>(L, adj), u, f, fc, uc, B, h->stream, (T *)h->dscr));
-    for (int g = 0; g < h->opt.gamma; ++g)
+    // (the coarse-level kernel runs several of the gamma visits per launch)
+    const int per = lv + 1 == h->tail_lv ? h->tail_reps : 1;
+    for (int g = 0; g < h->opt.gamma; g += per)
         if ((rc = cycle<T>(h, lv + 1, uc, fc, adj))) return rc;
     HIPCHK(launch_prolong_add<T>(L.d, C.d, uc, u, B, h->stream));
     for (int s = 0; s < h->opt.nu2; ++s)
