@@ -830,6 +830,22 @@ struct mg_handle {
     mg_options opt;
     hipStream_t stream = nullptr;
     SideStream side;          // overlaps big-block launches with the rest of a half-sweep
+    // One step of the solve loop (a cycle, or a refinement step, with the
+    // defect norm after it) captured as a HIP graph and replayed: one launch
+    // per step instead of one per kernel.  A capture is valid for its arrays,
+    // direction and precision while gen is unchanged; gen moves whenever the
+    // options, the workspace or the coarse-level images change.
+    struct {
+        bool enabled = true;
+        bool broken = false; // a capture failed: the solves stay eager
+        hipStream_t cap = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        const void *u = nullptr, *f = nullptr;
+        int adj = -1, prec = -1;
+        unsigned gen = 0;
+    } step;
+    unsigned gen = 1;
     int nlev = 0;
     Level lev[MAXLEV];
     int slot_motif[MAXSLOT] = {-1, -1, -1};
@@ -927,6 +943,7 @@ int ensure_workspace(mg_handle *h)
     if (hipMalloc(&p, h->ws_bytes) != hipSuccess) return MG_ENOMEM;
     h->ws = (char *)p;
     h->ws_owned = true;
+    ++h->gen;
     workspace_layout(h, true);
     return clear_workspace(h);
 }
@@ -1143,6 +1160,7 @@ void free_tail(mg_handle *h)
         }
     h->tail_lv = -1;
     h->tail_reps = 1;
+    ++h->gen;
     h->tail_map_lv[0] = h->tail_map_lv[1] = -1;
 }
 
@@ -1314,6 +1332,8 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
     int nl = 0;
     int orient = LAYOUT_ROW;
     {
+        const char *envg = std::getenv("TWMG_NO_GRAPH");
+        h->step.enabled = !(envg && envg[0] == '1');
         const char *env = std::getenv("TWMG_ROW_LAYOUT");
         const bool row_only = env && env[0] == '1';
         if (dim == 2 && !row_only) {
@@ -1675,6 +1695,66 @@ int read_norms(mg_handle *h, double *out)
 
 bool finite(double v) { return v == v && !std::isinf(v); }
 
+void drop_step_graph(mg_handle *h)
+{
+    if (h->step.exec) (void)hipGraphExecDestroy(h->step.exec);
+    if (h->step.graph) (void)hipGraphDestroy(h->step.graph);
+    h->step.exec = nullptr;
+    h->step.graph = nullptr;
+}
+
+// Runs one step of the solve loop on h->stream: replays its captured graph,
+// capturing it first (on a stream of the handle, with every launch of the
+// step, the side stream's included) when there is none for these arrays,
+// direction and precision.  A failed capture leaves the step eager for the
+// rest of the handle's life.
+template <typename F> int run_step(mg_handle *h, const void *u, const void *f, int adj, int prec, F &&step)
+{
+    auto &g = h->step;
+    // only steps on the workspace's own arrays (levels in a split layout) are
+    // captured: a caller's arrays may change from one solve to the next, and
+    // capturing anew for each solve would cost more than it saves
+    auto in_ws = [&](const void *p) {
+        const char *c = static_cast<const char *>(p);
+        return h->ws && c >= h->ws && c < h->ws + h->ws_bytes;
+    };
+    if (!g.enabled || g.broken || !in_ws(u) || !in_ws(f)) return step();
+    if (!g.exec || g.u != u || g.f != f || g.adj != adj || g.prec != prec || g.gen != h->gen) {
+        drop_step_graph(h);
+        if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) {
+            g.broken = true;
+            return step();
+        }
+        // (capturing runs nothing: the graph runs where it is launched)
+        hipStream_t keep = h->stream;
+        h->stream = g.cap;
+        hipError_t e = hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? step() : MG_EHIP;
+        hipGraph_t graph = nullptr;
+        if (e == hipSuccess) e = hipStreamEndCapture(g.cap, &graph);
+        h->stream = keep;
+        if (e == hipSuccess && rc == MG_OK) {
+            g.graph = graph;
+            e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        } else if (graph) {
+            (void)hipGraphDestroy(graph);
+        }
+        if (e != hipSuccess || rc != MG_OK || !g.exec) {
+            (void)hipGetLastError();
+            drop_step_graph(h);
+            g.broken = true;
+            return step();
+        }
+        g.u = u;
+        g.f = f;
+        g.adj = adj;
+        g.prec = prec;
+        g.gen = h->gen;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, h->stream));
+    return MG_OK;
+}
+
 int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *stats, int adj)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1709,17 +1789,23 @@ int solve_impl(mg_handle *h, double *u, const double *f, double tol, mg_stats *s
     if (bad0) status = MG_EDIVERGED;
     else if (any) {
         status = MG_ENOTCONV;
-        while (k < h->opt.max_cycles) {
+        // one step: a cycle (with refinement: e = FP32 cycle on A e = r from
+        // 0, r = f - A u from the last defect pass rounded to FP32, then
+        // u += e), then the defect pass
+        auto step = [&]() -> int {
+            int r;
             if (ir) {
-                // e = FP32 cycle on A e = r from 0, r = f - A u (FP64, from the
-                // last defect pass) rounded to FP32; u += e
                 HIPCHK(launch_fill<float>(L.u32, L.d.bs * B, 0.0f, h->stream));
-                if ((rc = cycle<float>(h, 0, L.u32, L.f32, adj))) return rc;
+                if ((r = cycle<float>(h, 0, L.u32, L.f32, adj))) return r;
                 HIPCHK(launch_ir_update(L.d, u, L.u32, B, h->stream));
             } else {
-                if ((rc = cycle<double>(h, 0, u, f, adj))) return rc;
+                if ((r = cycle<double>(h, 0, u, f, adj))) return r;
             }
             HIPCHK(defect_norm());
+            return MG_OK;
+        };
+        while (k < h->opt.max_cycles) {
+            if ((rc = run_step(h, u, f, adj, ir ? 1 : 0, step))) return rc;
             if ((rc = read_norms(h, d.data()))) return rc;
             rel = 0.0;
             bool bad = false;
@@ -1806,6 +1892,8 @@ void mg_destroy(mg_handle *h)
     else (void)hipDeviceSynchronize();
     if (h->ws_owned && h->ws) (void)hipFree(h->ws);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
+    drop_step_graph(h);
+    if (h->step.cap) (void)hipStreamDestroy(h->step.cap);
     free_tail(h);
     if (h->side.aux) (void)hipStreamSynchronize(h->side.aux);
     if (h->side.fork) (void)hipEventDestroy(h->side.fork);
@@ -1835,6 +1923,7 @@ int mg_set_options(mg_handle *h, const mg_options *opt)
             if (m[s] != h->slot_motif[s]) return MG_EINVAL;
     h->opt = *opt;
     h->checker = ck;
+    ++h->gen;
     return build_tail(h);
 }
 
@@ -1850,6 +1939,7 @@ int mg_bind_workspace(mg_handle *h, void *dev_ptr, size_t bytes)
     }
     h->ws = (char *)dev_ptr;
     h->ws_owned = false;
+    ++h->gen;
     workspace_layout(h, true);
     return clear_workspace(h);
 }
