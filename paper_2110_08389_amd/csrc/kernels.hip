@@ -817,8 +817,8 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
             hipLaunchKernelGGL((k_block_sweep<T, DIM, NT / 2, DOFF>), grid, dim3(NT / 2), 0, ss, d, c, u, f,
                                tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
         } else {
-            if constexpr (DIM == 2) {
-                // narrow workgroups (2D levels bound by a workgroup's latency),
+            {
+                // narrow workgroups (levels bound by a workgroup's latency),
                 // with chunks of up to 16 or of up to 8 points
                 if (tab.nts == 64 && tab.cap == CH)
                     hipLaunchKernelGGL((k_block_sweep<T, DIM, 64, DOFF>), grid, dim3(64), 0, ss, d, c, u, f,
@@ -837,8 +837,6 @@ static hipError_t launch_sweep_dim(const Dims &d, const Coef<T> &c, T *u, const 
                                        u, f, tab.chunks, recs, cross, tab.blocks, wsm, fac, rings);
                 else
                     return hipErrorInvalidValue;
-            } else {
-                return hipErrorInvalidValue;
             }
         }
     }

@@ -1453,7 +1453,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             const bool tail_size = L.d.nn * 2 * (long long)sizeof(double) <= TAIL_BYTES;
             int nmax = 0;
             for (int a = 0; a < dim; ++a) nmax = std::max(nmax, L.d.n[a]);
-            const bool short_main = dim == 2 && !tail_size && nmax <= SHORT_CH_MAXN;
+            const bool short_main = !tail_size && nmax <= (dim == 2 ? SHORT_CH_MAXN : SHORT_CH_MAXN3);
             const int maxlen =
                 !tail_size ? (short_main ? SHORT_CH : CH) : (nmax <= TAIL_SHORT_MAXN ? TAIL_SHORT_CH : CH - 1);
             std::vector<HostBlock> blocks, short_blocks;
@@ -1462,7 +1462,7 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
             // on the larger 2D levels, a colour whose blocks all still fit
             // NT/2 lanes with chunks of SHORT_CH points takes those (shorter
             // chains per lane; a colour with a larger block keeps CH)
-            bool short_colour[2] = {maxlen <= SHORT_CH && dim == 2, maxlen <= SHORT_CH && dim == 2};
+            bool short_colour[2] = {maxlen <= SHORT_CH, maxlen <= SHORT_CH};
             if (dim == 2 && !tail_size && maxlen == CH) {
                 rc = build_blocks(L.g, h->slot_motif[s], short_blocks, SHORT_CH);
                 if (rc == MG_EUNSUPPORTED) short_blocks.clear(); // a block beyond NT chunks
@@ -1480,8 +1480,9 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                     if (hb.colour == colour) sel.push_back(&hb);
                 HostTable &t = L.htab[s][colour];
                 // narrow workgroups for 2D levels too large for the
-                // coarse-level kernel (whose sweeps use NT/2 lanes)
-                const bool narrow = dim == 2 && !tail_size;
+                // coarse-level kernel (whose sweeps use NT/2 lanes) and for
+                // the 3D levels with short chunks
+                const bool narrow = !tail_size && (dim == 2 || short_main);
                 pack(sel, t, narrow);
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;

@@ -15,10 +15,11 @@ constexpr int CH = 16;
 // spare entries on each side of a device coefficient block (a multiple of 2,
 // at least the CH + 2 entries of a chunk's coefficient window)
 constexpr int COEF_PAD = CH + 2;
-// chunk capacity on the 2D levels whose sweeps are bound by one workgroup's
+// chunk capacity on the levels whose sweeps are bound by one workgroup's
 // latency (the lane's serial chains and its gather batches are half as long)
 constexpr int SHORT_CH = 8;
-constexpr int SHORT_CH_MAXN = 1024; // levels with at most this many cells per axis
+constexpr int SHORT_CH_MAXN = 1024; // 2D levels with at most this many cells per axis
+constexpr int SHORT_CH_MAXN3 = 128; // 3D levels with at most this many cells per axis
 // motif slots: the sweeps of one relaxation (three for 3D alternating-direction
 // zebra: lines along x, then y, then z)
 constexpr int MAXSLOT = 3;
@@ -241,8 +242,8 @@ struct SweepTable {
     NodeFac<float> *fac32[2] = {nullptr, nullptr};
     int nwg = 0, nchunk = 0, nblock = 0;
     int nwg_big = 0; // the first nwg_big workgroups need NT lanes, the others nts
-    int nts = NT / 2; // lanes of the small workgroups: 64, 128 or NT/2 (2D only below NT/2)
-    int cap = CH;     // longest chunk: CH, or SHORT_CH (2D levels bound by a workgroup's latency)
+    int nts = NT / 2; // lanes of the small workgroups: 64, 128 or NT/2
+    int cap = CH;     // longest chunk: CH, or SHORT_CH (levels bound by a workgroup's latency)
     bool rings = false;
 };
 
