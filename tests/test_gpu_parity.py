@@ -59,7 +59,9 @@ def test_level_coefficients_match_oracle():
                 assert rel_inf(xg, xo) < 1e-15 and rel_inf(log, loo) < 1e-14 and rel_inf(hig, hio) < 1e-14
 
 
-@pytest.mark.parametrize("n,kind,c", CASES_2D + [([16, 16, 16], "tanh_wall", 2.5), ([24, 16, 32], "tanh_wall", 2.0)])
+@pytest.mark.parametrize("n,kind,c", CASES_2D + [([16, 16, 16], "tanh_wall", 2.5), ([24, 16, 32], "tanh_wall", 2.0),
+                                                  ([64, 64, 64], "tanh_wall", 2.5), ([96, 64, 80], "tanh_wall", 2.0),
+                                                  ([80, 64, 72], "sinh_centre", 3.0)])
 def test_residual_restrict_prolong(n, kind, c):
     s = solver(n, kind, c, "tweed")
     H = ohier(n, kind, c, "tweed")
