@@ -1479,10 +1479,9 @@ int setup_impl(mg_handle *h, const mg_grid *grid, const mg_stretching *st, const
                 for (const HostBlock &hb : short_colour[colour] && maxlen == CH ? short_blocks : blocks)
                     if (hb.colour == colour) sel.push_back(&hb);
                 HostTable &t = L.htab[s][colour];
-                // narrow workgroups for 2D levels too large for the
-                // coarse-level kernel (whose sweeps use NT/2 lanes) and for
-                // the 3D levels with short chunks
-                const bool narrow = !tail_size && (dim == 2 || short_main);
+                // narrow workgroups for the levels too large for the
+                // coarse-level kernel (whose sweeps use NT/2 lanes)
+                const bool narrow = !tail_size;
                 pack(sel, t, narrow);
                 if (!validate(L.g, t)) return MG_EUNSUPPORTED;
                 int err = 0;
