@@ -1302,9 +1302,8 @@ __device__ __forceinline__ void tile3_plane(const Dims &d, int f0, int a0, int b
 // (a caller's row-major array) decode the tile number.  The plane is uniform
 // per workgroup and a template argument below the branch, so no coordinate is
 // picked by a run-time axis index.
-template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int k, Op &&op)
+template <int NB> __device__ __forceinline__ void tile3_decode(const Dims &d, int k, int &pl, int &f0, int &a0, int &b0)
 {
-    int pl, f0, a0, b0;
     if (d.tiles) {
         const Tile3E e = d.tiles[k];
         pl = e.x & 3;
@@ -1319,6 +1318,11 @@ template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const
         a0 = ((k / tf) % ta) * 4;
         b0 = (k / (tf * ta)) * (4 * NB);
     }
+}
+template <int NB, typename Op> __device__ __forceinline__ void tile3_visit(const Dims &d, int k, Op &&op)
+{
+    int pl, f0, a0, b0;
+    tile3_decode<NB>(d, k, pl, f0, a0, b0);
     if (pl == 0)
         tile3_plane<0, NB>(d, f0, a0, b0, op);
     else if (pl == 1)
@@ -1485,23 +1489,128 @@ __device__ __forceinline__ void col_defects(const Dims &d, const Coef<T> &cf, co
     }
 }
 
+// Defects of a thread's column (as col_defects) with u read from a box
+// staged in LDS: the workgroup's tile of plane PL at (F0, A0, B0) plus a
+// one-node halo, BX_F x BX_A x BX_B nodes in (F, A, B) order, each read once
+// from its own slot whatever plane keeps it (0 off the grid).  A wavefront's
+// loads then cover runs along F, and a node's six neighbours come from LDS
+// instead of six more loads through the vector cache.  Every thread of the
+// workgroup calls it (it synchronises the workgroup); c receives the
+// thread's column (no node of a column off the grid is ok).  Same summation
+// order as defect_at.
+constexpr int BX_F = 16 + 2, BX_A = 4 + 2, BX_B = 4 * COL_NB + 2, BX_N = BX_F * BX_A * BX_B;
+template <typename T, int PL>
+__device__ __forceinline__ void tile3_defects(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
+                                              const T *__restrict__ fb, int F0, int A0, int B0, T *s_u,
+                                              Col3<COL_NB> &c, T (&out)[COL_NB])
+{
+    using X = PlaneAxes<PL>;
+    constexpr int NB = COL_NB, NQ = (BX_N + 255) / 256;
+    const int t = threadIdx.x;
+    const int f = F0 + (t & 15), a = A0 + ((t >> 4) & 3), b = B0 + NB * (t >> 6);
+    const bool colin = f <= d.n[X::F] && a <= d.n[X::A];
+    c = col3<PL, NB>(d, colin ? f : 0, colin ? a : 0, b);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        c.ok[k] = c.ok[k] && colin;
+        c.in[k] = c.in[k] && colin;
+    }
+    // every load of the tile issued before any is used: the box, the
+    // column's f, the coefficients
+    T v[NQ];
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const int q = t + 256 * r;
+        const int qq = q < BX_N ? q : 0;
+        int cc[3];
+        cc[X::F] = F0 - 1 + qq % BX_F;
+        cc[X::A] = A0 - 1 + (qq / BX_F) % BX_A;
+        cc[X::B] = B0 - 1 + qq / (BX_F * BX_A);
+        const bool in = q < BX_N && cc[0] >= 0 && cc[0] <= d.n[0] && cc[1] >= 0 && cc[1] <= d.n[1] &&
+                        cc[2] >= 0 && cc[2] <= d.n[2];
+        const T val = ub[slot3(d, in ? cc[0] : 0, in ? cc[1] : 0, in ? cc[2] : 0)];
+        v[r] = in ? val : T(0);
+    }
+    T fv[NB], lb[NB], hb[NB], gb[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        fv[k] = fb[c.in[k] ? c.sl[k] : 0];
+        const int bk = min(b + k, d.n[X::B]);
+        lb[k] = cf.lo[X::B][bk];
+        hb[k] = cf.hi[X::B][bk];
+        gb[k] = cf.dg[X::B][bk];
+    }
+    const int fc = min(f, d.n[X::F]), ac = min(a, d.n[X::A]);
+    const T lf = cf.lo[X::F][fc], hf = cf.hi[X::F][fc], gf = cf.dg[X::F][fc];
+    const T la = cf.lo[X::A][ac], ha = cf.hi[X::A][ac], ga = cf.dg[X::A][ac];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const int q = t + 256 * r;
+        if (q < BX_N) s_u[q] = v[r];
+    }
+    __syncthreads();
+    int st[3];
+    st[X::F] = 1;
+    st[X::A] = BX_F;
+    st[X::B] = BX_F * BX_A;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int p = (1 + NB * (t >> 6) + k) * (BX_F * BX_A) + (1 + ((t >> 4) & 3)) * BX_F + 1 + (t & 15);
+        T lo[3], hi[3], dg[3];
+        lo[X::F] = lf;
+        hi[X::F] = hf;
+        dg[X::F] = gf;
+        lo[X::A] = la;
+        hi[X::A] = ha;
+        dg[X::A] = ga;
+        lo[X::B] = lb[k];
+        hi[X::B] = hb[k];
+        dg[X::B] = gb[k];
+        T sum = lo[0] * s_u[p - st[0]] + hi[0] * s_u[p + st[0]];
+        sum += lo[1] * s_u[p - st[1]] + hi[1] * s_u[p + st[1]];
+        T g = dg[0] + dg[1];
+        sum += lo[2] * s_u[p - st[2]] + hi[2] * s_u[p + st[2]];
+        g += dg[2];
+        out[k] = c.in[k] ? fv[k] - (sum + g * s_u[p]) : T(0);
+    }
+}
+
+// Runs body(PlaneC<PL>(), F0, A0, B0) for each tile of the workgroup's
+// grid-stride iterations, with the whole workgroup (after a barrier, so that
+// the previous tile's LDS reads are done)
+template <typename Body> __device__ __forceinline__ void tile3_wg_loop(const Dims &d, Body &&body)
+{
+    const int nt = tile3_count<COL_NB>(d);
+    for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+        int pl, F0, A0, B0;
+        tile3_decode<COL_NB>(d, tile3_index(it, nt), pl, F0, A0, B0);
+        __syncthreads();
+        if (pl == 0)
+            body(PlaneC<0>(), F0, A0, B0);
+        else if (pl == 1)
+            body(PlaneC<1>(), F0, A0, B0);
+        else
+            body(PlaneC<2>(), F0, A0, B0);
+    }
+}
+
 // defect d = f - L u of every node (0 on boundary nodes) into r (layout of d)
 template <typename T>
 __global__ void __launch_bounds__(256) k_residual3(Dims d, Coef<T> cf, const T *__restrict__ u,
                                                    const T *__restrict__ f, T *__restrict__ r)
 {
+    __shared__ T s_u[BX_N];
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tile3_count<COL_NB>(d);
-    for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
-            constexpr int PL = decltype(plc)::value;
-            const Col3<COL_NB> c = col3<PL, COL_NB>(d, fq, aq, bq);
-            T dv[COL_NB];
-            col_defects<T, PL, COL_NB>(d, cf, u + boff, f + boff, c, dv);
+    tile3_wg_loop(d, [&](auto plc, int F0, int A0, int B0) {
+        constexpr int PL = decltype(plc)::value;
+        Col3<COL_NB> c;
+        T dv[COL_NB];
+        tile3_defects<T, PL>(d, cf, u + boff, f + boff, F0, A0, B0, s_u, c, dv);
 #pragma unroll
-            for (int k = 0; k < COL_NB; ++k)
-                if (c.ok[k]) r[boff + c.sl[k]] = dv[k];
-        });
+        for (int k = 0; k < COL_NB; ++k)
+            if (c.ok[k]) r[boff + c.sl[k]] = dv[k];
+    });
 }
 
 // per-workgroup maximum of |f - L u| over interior nodes (optionally the
@@ -1511,24 +1620,23 @@ __global__ void __launch_bounds__(256) k_resnorm3(Dims d, Coef<T> cf, const T *_
                                                   const T *__restrict__ f, float *__restrict__ r32,
                                                   double *__restrict__ partial)
 {
+    __shared__ T s_u[BX_N];
     const long long boff = (long long)blockIdx.y * d.bs;
-    const int nt = tile3_count<COL_NB>(d);
     double m = 0.0;
     bool nan = false;
-    for (int it = blockIdx.x; it < nt; it += gridDim.x)
-        tile3_visit<COL_NB>(d, tile3_index(it, nt), [&](auto plc, int fq, int aq, int bq) {
-            constexpr int PL = decltype(plc)::value;
-            const Col3<COL_NB> c = col3<PL, COL_NB>(d, fq, aq, bq);
-            T dv[COL_NB];
-            col_defects<T, PL, COL_NB>(d, cf, u + boff, f + boff, c, dv);
+    tile3_wg_loop(d, [&](auto plc, int F0, int A0, int B0) {
+        constexpr int PL = decltype(plc)::value;
+        Col3<COL_NB> c;
+        T dv[COL_NB];
+        tile3_defects<T, PL>(d, cf, u + boff, f + boff, F0, A0, B0, s_u, c, dv);
 #pragma unroll
-            for (int k = 0; k < COL_NB; ++k) {
-                if (TO32 && c.ok[k]) r32[boff + c.sl[k]] = (float)dv[k];
-                const double av = fabs((double)dv[k]);
-                nan = nan || (av != av);
-                m = fmax(m, av);
-            }
-        });
+        for (int k = 0; k < COL_NB; ++k) {
+            if (TO32 && c.ok[k]) r32[boff + c.sl[k]] = (float)dv[k];
+            const double av = fabs((double)dv[k]);
+            nan = nan || (av != av);
+            m = fmax(m, av);
+        }
+    });
     if (nan) m = __builtin_inf();
     m = block_max(m);
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
