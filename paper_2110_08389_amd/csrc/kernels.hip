@@ -1243,16 +1243,6 @@ template <int PL> __device__ __forceinline__ int slot_in_plane(const Dims &d, in
     if (PL == 1) return nn + j + S1 * (i + S0 * l);
     return 2 * nn + l + S2 * (i + S0 * j);
 }
-// strides of the A and B axes in plane PL (F has stride 1); the row-major
-// layout is plane 0
-template <int PL> __device__ __forceinline__ int stride_a(const Dims &d)
-{
-    return PL == 0 ? d.n[0] + 1 : (PL == 1 ? d.n[1] + 1 : d.n[2] + 1);
-}
-template <int PL> __device__ __forceinline__ int stride_b(const Dims &d)
-{
-    return (d.n[0] + 1) * (PL == 0 ? d.n[1] + 1 : (PL == 1 ? d.n[1] + 1 : d.n[2] + 1));
-}
 // (i, j, l) of the node at (f, a, b) in plane PL's axes
 template <int PL> __device__ __forceinline__ void plane_xyz(int f, int a, int b, int &i, int &j, int &l)
 {
@@ -1264,16 +1254,6 @@ template <int PL> __device__ __forceinline__ void plane_xyz(int f, int a, int b,
     i = c[0];
     j = c[1];
     l = c[2];
-}
-// how far node (i, j, l), kept in plane PL, lies inside the plane's region
-// (as P3::margin); large for the row-major layout
-template <int PL> __device__ __forceinline__ int margin3(const Dims &d, int i, int j, int l)
-{
-    if (d.layout != LAYOUT_TWEED3) return 1 << 20;
-    const int ip = min(i, d.n[0] - i), jp = min(j, d.n[1] - j), lp = min(l, d.n[2] - l);
-    const int own = PL == 0 ? ip : (PL == 1 ? jp : lp);
-    const int o1 = PL == 0 ? jp : ip, o2 = PL == 2 ? jp : lp;
-    return min(o1, o2) - own;
 }
 
 // The tile of plane PL at (f0, a0, b0) (along F, A, B): this thread's column
@@ -1410,87 +1390,8 @@ __device__ __forceinline__ int slot3(const Dims &d, int i, int j, int l) { retur
 // box per fine plane of its column, so it holds fewer)
 constexpr int COL_NB = 2, COL_NB_RESTRICT = 2;
 
-// Defects of a column's nodes (0 where not interior).  A node whose six
-// neighbours share its plane finds them at the plane's strides; nearer the
-// plane's border each neighbour's slot is computed in general form.  The
-// coefficients along F and A are the column's, read once, and every load is
-// issued before the arithmetic.  Same summation order as defect_at.
-template <typename T, int PL, int NB>
-__device__ __forceinline__ void col_defects(const Dims &d, const Coef<T> &cf, const T *__restrict__ ub,
-                                            const T *__restrict__ fb, const Col3<NB> &c, T (&out)[NB])
-{
-    using X = PlaneAxes<PL>;
-    const int sa = stride_a<PL>(d), sb = stride_b<PL>(d);
-    // a slot whose neighbours at the plane's strides stay inside the plane,
-    // for nodes that are not interior (their result is dropped)
-    const int safe = PL * (int)d.nn + sb + sa + 1;
-    int cc[3];
-    cc[0] = c.i[0];
-    cc[1] = c.j[0];
-    cc[2] = c.l[0];
-    const int f = cc[X::F], a = cc[X::A], b = cc[X::B];
-    T uv[NB][7], fv[NB], lb[NB], hb[NB], gb[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const bool in = c.in[k];
-        const bool reg = !in || margin3<PL>(d, c.i[k], c.j[k], c.l[k]) >= 2;
-        const int p = in ? c.sl[k] : safe;
-        // neighbours toward - and + along x, y, z
-        int nb[6];
-        int st[3];
-        st[X::F] = 1;
-        st[X::A] = sa;
-        st[X::B] = sb;
-        if (reg) {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                nb[2 * ax] = p - st[ax];
-                nb[2 * ax + 1] = p + st[ax];
-            }
-        } else {
-            const int i = c.i[k], j = c.j[k], l = c.l[k];
-            nb[0] = slot3(d, i - 1, j, l);
-            nb[1] = slot3(d, i + 1, j, l);
-            nb[2] = slot3(d, i, j - 1, l);
-            nb[3] = slot3(d, i, j + 1, l);
-            nb[4] = slot3(d, i, j, l - 1);
-            nb[5] = slot3(d, i, j, l + 1);
-        }
-        uv[k][0] = ub[p];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) uv[k][m + 1] = ub[nb[m]];
-        fv[k] = fb[p];
-        const int bk = min(b + k, d.n[X::B]);
-        lb[k] = cf.lo[X::B][bk];
-        hb[k] = cf.hi[X::B][bk];
-        gb[k] = cf.dg[X::B][bk];
-    }
-    const T lf = cf.lo[X::F][f], hf = cf.hi[X::F][f], gf = cf.dg[X::F][f];
-    const T la = cf.lo[X::A][a], ha = cf.hi[X::A][a], ga = cf.dg[X::A][a];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        T lo[3], hi[3], dg[3];
-        lo[X::F] = lf;
-        hi[X::F] = hf;
-        dg[X::F] = gf;
-        lo[X::A] = la;
-        hi[X::A] = ha;
-        dg[X::A] = ga;
-        lo[X::B] = lb[k];
-        hi[X::B] = hb[k];
-        dg[X::B] = gb[k];
-        T sum = lo[0] * uv[k][1] + hi[0] * uv[k][2];
-        sum += lo[1] * uv[k][3] + hi[1] * uv[k][4];
-        T g = dg[0] + dg[1];
-        sum += lo[2] * uv[k][5] + hi[2] * uv[k][6];
-        g += dg[2];
-        out[k] = c.in[k] ? fv[k] - (sum + g * uv[k][0]) : T(0);
-    }
-}
-
-// Defects of a thread's column (as col_defects) with u read from a box
-// staged in LDS: the workgroup's tile of plane PL at (F0, A0, B0) plus a
+// Defects of a thread's column of nodes (0 where not interior), with u read
+// from a box staged in LDS: the workgroup's tile of plane PL at (F0, A0, B0) plus a
 // one-node halo, BX_F x BX_A x BX_B nodes in (F, A, B) order, each read once
 // from its own slot whatever plane keeps it (0 off the grid).  A wavefront's
 // loads then cover runs along F, and a node's six neighbours come from LDS
