@@ -200,6 +200,30 @@ def test_dirichlet_data_and_batch():
         assert np.array_equal(ug[b][~H.interior_mask()], bc[b][~H.interior_mask()])
 
 
+def test_dirichlet_data_and_batch_3d_split_layout():
+    """A batch of two 3D problems on the three-plane layout (65^3 nodes) with
+    Dirichlet data: each problem's iterate after the batch's cycles equals the
+    oracle's after as many cycles, and its boundary holds the data."""
+    n, kind, c = [64, 64, 64], "tanh_wall", 2.5
+    B = 2
+    s = solver(n, kind, c, "tweed", batch=B)
+    H = ohier(n, kind, c, "tweed")
+    shape = H.shape(0)
+    f, bc, _ = inputs.normal_triplet((B,) + shape, 1005)
+    u, st = s.solve(T(f), T(bc), tol=1e-8)
+    assert st["status"] == 0
+    ug = N(u)
+    m = H.interior_mask()
+    for b in range(B):
+        g = bc[b].copy()
+        g[m] = 0.0
+        uo, kk, _, _ = H.solve(g, f[b], tol=0.0, max_cycles=st["cycles"])
+        assert kk == st["cycles"]
+        assert rel_inf(ug[b], uo) < 1e-12
+        assert H.resnorm(ug[b], f[b]) / H.resnorm(g, f[b]) < 1e-8
+        assert np.array_equal(ug[b][~m], bc[b][~m])
+
+
 def test_batch_stopping_rule_per_problem():
     """Section 4 stopping rule in a batch: each problem's defect is measured
     against its own initial defect.  Right-hand sides of very different sizes
@@ -231,7 +255,8 @@ def test_batch_stopping_rule_per_problem():
 # FP32-refinement cases: (n, stretching, smoother, gamma, seed)
 IR_CASES = [([256, 256], "sinh_centre", 4.0, "wireframe", 2, 1002),
             ([256, 256], "tanh_wall", 3.0, "tweed", 1, 1001),
-            ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1, 1003)]
+            ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1, 1003),
+            ([64, 64, 64], "tanh_wall", 2.5, "tweed", 1, 1003)]
 
 
 @pytest.mark.parametrize("n,kind,c,sm,gamma,seed", IR_CASES)
@@ -243,8 +268,9 @@ def test_mixed_precision_refinement(n, kind, c, sm, gamma, seed):
     the error the last cycle leaves (about rho times the one before it); the
     FP32 step adds its own rounding, a relative 2^-24 of the last correction,
     which is itself below 1e-9 of u.  The measured errors are 5e-14
-    (wireframe), 6e-15 (tweed) and 4e-16 (3D), printed; the bound 1e-11 leaves
-    two orders of margin or more."""
+    (wireframe), 6e-15 (tweed) and 3e-16 and 6e-16 (3D, 32^3 and the
+    three-plane 64^3), printed; the bound 1e-11 leaves two orders of margin
+    or more."""
     s = solver(n, kind, c, sm, gamma=gamma, precision="fp32_ir")
     H = ohier(n, kind, c, sm)
     f = inputs.uniform(H.shape(0), seed) if seed != 1002 else inputs.normal(H.shape(0), seed)
@@ -264,7 +290,8 @@ def test_mixed_precision_refinement(n, kind, c, sm, gamma, seed):
 @pytest.mark.parametrize("n,kind,c,sm,gamma,seed", [([256, 256], "tanh_wall", 3.0, "tweed", 1, 1004),
                                                     ([256, 256], "sinh_centre", 4.0, "wireframe", 2, 1004),
                                                     ([128, 96], "tanh_wall", 2.5, "tweed", 1, 1004),
-                                                    ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1, 1004)])
+                                                    ([32, 32, 32], "tanh_wall", 2.5, "tweed", 1, 1004),
+                                                    ([64, 64, 64], "tanh_wall", 2.5, "tweed", 1, 1004)])
 def test_adjoint_solve_same_cycles(n, kind, c, sm, gamma, seed):
     """mg_solve_adjoint (transposed operator, colours reversed, from 0) against
     the oracle's cycle on the transposed operator: the same number of cycles to
